@@ -1,0 +1,197 @@
+/*
+ * CPU oracle of the nine-cluster local noise filter.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * statement of what the filter computes; it exists so that the HIP path can be
+ * checked against it.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code, header, table or helper
+ * with the GPU library.
+ *
+ * What is computed (paper, Section "Our Method", equations 2 and 3, and the
+ * figure of the nine average clusters):
+ *   - an "average cluster" is the mean of a cubic region of side M = 2r+1 around
+ *     a centre voxel; offsets run over i - (M-1)/2 for i = 0..M-1 (eq. 3);
+ *   - S_0 is the cluster about the voxel itself; S_1..S_8 sit on the eight
+ *     diagonal neighbours, sqrt(3) units away when M = 3 (r = 1).  For larger r
+ *     the diagonal centres are placed at (+-r, +-r, +-r), so that each diagonal
+ *     cluster is the octant box that still touches the centre voxel;
+ *   - the voxel is replaced by the average of the nine cluster averages
+ *     (rule MEAN9), rounded to the nearest integer;
+ *   - values below a data threshold T (Otsu's, eq. 1) are noise: written as 0.
+ * Rule MINVAR9 is not in the paper: it picks the cluster of least variance
+ * (numerator n*sum(x^2) - (sum x)^2, lowest cluster index on ties) and writes
+ * its rounded mean.
+ *
+ * Readings where the paper is silent: samples outside the volume take the value
+ * of the nearest voxel (clamp each coordinate separately); rounding is
+ * round-half-up, and no exact half can occur because both divisors (9n and n,
+ * n = M^3) are odd; the output has the dtype of the input.
+ *
+ * Cluster index order: k = 0 is the centre; for k = 1..8, with j = k-1, bit 0
+ * of j selects +r (else -r) along x, bit 1 along y, bit 2 along z.
+ *
+ * Volume layout: vol[z][y][x], x fastest; dtype 1 = uint8, 2 = uint16.
+ */
+#include <stdint.h>
+#include <stddef.h>
+
+#define LNFO_MEAN9 0
+#define LNFO_MINVAR9 1
+
+typedef struct {
+    const void* vol;
+    int64_t nx, ny, nz;
+    int dtype;
+} grid_t;
+
+static int64_t clamp_index(int64_t v, int64_t n)
+{
+    if (v < 0) return 0;
+    if (v > n - 1) return n - 1;
+    return v;
+}
+
+/* Grey value of the voxel nearest to (x, y, z), which may lie outside the volume. */
+static uint64_t sample(const grid_t* g, int64_t x, int64_t y, int64_t z)
+{
+    int64_t cx = clamp_index(x, g->nx);
+    int64_t cy = clamp_index(y, g->ny);
+    int64_t cz = clamp_index(z, g->nz);
+    int64_t idx = (cz * g->ny + cy) * g->nx + cx;
+    if (g->dtype == 1) return ((const uint8_t*)g->vol)[idx];
+    return ((const uint16_t*)g->vol)[idx];
+}
+
+/* Centre offset of cluster k (see the index order above). */
+static void cluster_offset(int k, int r, int64_t d[3])
+{
+    if (k == 0) {
+        d[0] = d[1] = d[2] = 0;
+        return;
+    }
+    int j = k - 1;
+    for (int axis = 0; axis < 3; ++axis)
+        d[axis] = ((j >> axis) & 1) ? r : -r;
+}
+
+/* Sum and sum of squares of the (2r+1)^3 region of every cluster about (px,py,pz). */
+static void cluster_stats(const grid_t* g, int r, int64_t px, int64_t py, int64_t pz,
+                          uint64_t s[9], uint64_t q[9])
+{
+    for (int k = 0; k < 9; ++k) {
+        int64_t d[3];
+        cluster_offset(k, r, d);
+        uint64_t sum = 0, sq = 0;
+        for (int64_t az = -r; az <= r; ++az)
+            for (int64_t ay = -r; ay <= r; ++ay)
+                for (int64_t ax = -r; ax <= r; ++ax) {
+                    uint64_t v = sample(g, px + d[0] + ax, py + d[1] + ay, pz + d[2] + az);
+                    sum += v;
+                    sq += v * v;
+                }
+        s[k] = sum;
+        q[k] = sq;
+    }
+}
+
+static uint32_t filter_voxel(const grid_t* g, int r, int rule, uint32_t gate_T,
+                             int64_t px, int64_t py, int64_t pz)
+{
+    uint64_t s[9], q[9];
+    cluster_stats(g, r, px, py, pz, s, q);
+    const uint64_t n = (uint64_t)(2 * r + 1) * (2 * r + 1) * (2 * r + 1);
+    uint64_t out;
+    if (rule == LNFO_MEAN9) {
+        /* mean of the nine cluster means = (sum of all nine sums) / (9n), rounded */
+        uint64_t total = 0;
+        for (int k = 0; k < 9; ++k) total += s[k];
+        out = (2 * total + 9 * n) / (18 * n);
+    } else {
+        /* n^2 times the variance of each cluster; all quantities below 2^62 for r <= 8 */
+        int best = 0;
+        int64_t best_v = 0;
+        for (int k = 0; k < 9; ++k) {
+            int64_t v = (int64_t)(n * q[k]) - (int64_t)(s[k] * s[k]);
+            if (k == 0 || v < best_v) {
+                best = k;
+                best_v = v;
+            }
+        }
+        out = (2 * s[best] + n) / (2 * n);
+    }
+    if (out < gate_T) out = 0;
+    return (uint32_t)out;
+}
+
+static int check_args(const void* vol, int64_t nx, int64_t ny, int64_t nz, int dtype, int r,
+                      int rule)
+{
+    if (!vol || nx < 1 || ny < 1 || nz < 1) return -1;
+    if (dtype != 1 && dtype != 2) return -1;
+    if (r < 1 || r > 8) return -1;
+    if (rule != LNFO_MEAN9 && rule != LNFO_MINVAR9) return -1;
+    return 0;
+}
+
+/* Filter a whole volume; `out` has the dtype and layout of `vol`. */
+int lnfo_filter(const void* vol, int64_t nx, int64_t ny, int64_t nz, int dtype, int r,
+                int rule, uint32_t gate_T, void* out)
+{
+    if (check_args(vol, nx, ny, nz, dtype, r, rule) || !out) return -1;
+    grid_t g = {vol, nx, ny, nz, dtype};
+    int64_t plane = nx * ny;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t zy = 0; zy < nz * ny; ++zy) {
+        int64_t z = zy / ny, y = zy % ny;
+        for (int64_t x = 0; x < nx; ++x) {
+            uint32_t v = filter_voxel(&g, r, rule, gate_T, x, y, z);
+            int64_t idx = z * plane + y * nx + x;
+            if (dtype == 1) ((uint8_t*)out)[idx] = (uint8_t)v;
+            else ((uint16_t*)out)[idx] = (uint16_t)v;
+        }
+    }
+    return 0;
+}
+
+/* Filter the voxels listed in xyz[m][3] (x, y, z inside the volume) into out[m]. */
+int lnfo_filter_points(const void* vol, int64_t nx, int64_t ny, int64_t nz, int dtype, int r,
+                       int rule, uint32_t gate_T, const int64_t* xyz, int64_t m, uint32_t* out)
+{
+    if (check_args(vol, nx, ny, nz, dtype, r, rule) || (m > 0 && (!xyz || !out))) return -1;
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+        if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) return -1;
+    }
+    grid_t g = {vol, nx, ny, nz, dtype};
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < m; ++i)
+        out[i] = filter_voxel(&g, r, rule, gate_T, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+    return 0;
+}
+
+/* The nine (sum, sum of squares) pairs at one voxel, for diagnostics and pins. */
+int lnfo_cluster_stats(const void* vol, int64_t nx, int64_t ny, int64_t nz, int dtype, int r,
+                       int64_t x, int64_t y, int64_t z, uint64_t* s9, uint64_t* q9)
+{
+    if (check_args(vol, nx, ny, nz, dtype, r, LNFO_MEAN9) || !s9 || !q9) return -1;
+    grid_t g = {vol, nx, ny, nz, dtype};
+    cluster_stats(&g, r, x, y, z, s9, q9);
+    return 0;
+}
+
+/* Number of OpenMP threads a parallel region of this library uses. */
+int lnfo_threads(void)
+{
+    int t = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        {
+#ifdef _OPENMP
+            extern int omp_get_num_threads(void);
+            t = omp_get_num_threads();
+#endif
+        }
+    }
+    return t;
+}
