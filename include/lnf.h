@@ -1,0 +1,133 @@
+/*
+ * lnf.h -- C ABI of the MI355X (gfx950) local noise filter for 3D CT volumes.
+ *
+ * The filter (Tan Jerome et al., "Real-time Local Noise Filter in 3D
+ * Visualization of CT Data", Section "Our Method", eqs. 2-3 and the figure of
+ * the nine "average clusters"): every voxel is replaced by a combination of
+ * nine cubic sub-regions ("average clusters") of side M = 2r+1 -- S_0 centred
+ * on the voxel and S_1..S_8 centred on its diagonal neighbours at (+-r,+-r,+-r),
+ * which is sqrt(3) units away for the paper's M = 3.  Values below the data
+ * threshold T (Otsu's, eq. 1) are treated as noise and written as 0.
+ *
+ * Exact integer semantics (identical on every call, tile shape and batch mix):
+ *   n      = (2r+1)^3
+ *   s_k    = sum of the n voxels of cluster k, q_k = sum of their squares
+ *   sample = voxel at the coordinate clamped into the volume, per axis
+ *   LNF_MEAN9   (the paper's rule): out = round(sum_k s_k / (9n))
+ *   LNF_MINVAR9 (not in the paper; least-variance selection): k* = the lowest k
+ *               minimising n*q_k - s_k^2, out = round(s_k* / n)
+ *   gate        out = (out >= T) ? out : 0   (T = 0 disables it)
+ * Rounding is to nearest; no exact half can occur because 9n and n are odd.
+ * Cluster order: k = 0 is the centre; for k = 1..8 with j = k-1, bit 0 of j
+ * selects +r (else -r) along x, bit 1 along y, bit 2 along z.
+ *
+ * Volumes are dense, x fastest: element (x,y,z) at byte offset
+ * ((z*ny + y)*nx + x) * sizeof(element).  dims[] = {nx, ny, nz}.
+ *
+ * All functions return LNF_OK (0) or a negative LNF_E* code and never throw or
+ * abort across the ABI.  Work is enqueued asynchronously on the given stream;
+ * device-side faults surface at the caller's next synchronisation.
+ */
+#ifndef LNF_H
+#define LNF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define LNF_API __attribute__((visibility("default")))
+#else
+#define LNF_API
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define LNF_OK 0
+#define LNF_EINVAL (-1)     /* bad argument: null pointer, dtype, radius, dims, overlap */
+#define LNF_EDEVICE (-2)    /* a pointer is not device memory of the handle's device */
+#define LNF_ENOMEM (-3)     /* library-internal allocation failed */
+#define LNF_EHIP (-4)       /* a HIP runtime call or kernel launch failed */
+#define LNF_EBUSY (-5)      /* server: admission would exceed the memory cap */
+#define LNF_ENOTFOUND (-6)  /* server: unknown volume id or ticket */
+#define LNF_ECANCELED (-7)  /* server: request was cancelled or its batch failed */
+#define LNF_ETIMEDOUT (-8)  /* server: wait timed out (request still pending) */
+
+/* ---- enumerations ---------------------------------------------------- */
+#define LNF_U8 1            /* uint8 voxels */
+#define LNF_U16 2           /* uint16 voxels */
+
+#define LNF_MEAN9 0         /* mean of the nine cluster means (the paper's rule) */
+#define LNF_MINVAR9 1       /* mean of the least-variance cluster (not in the paper) */
+
+#define LNF_RADIUS_MAX 4    /* largest supported r (cluster side M = 2r+1 <= 9) */
+
+/* ---- context ----------------------------------------------------------- */
+typedef struct lnf_ctx* lnf_handle;
+
+typedef struct {
+    uint32_t size;    /* sizeof(lnf_options), for forward compatibility */
+    int32_t rule;     /* LNF_MEAN9 (default) or LNF_MINVAR9 */
+    uint32_t gate_T;  /* data threshold T of the noise gate; 0 disables the gate */
+    int32_t device;   /* HIP device ordinal; -1 = the device current at create time */
+    uint32_t flags;   /* reserved, must be 0 */
+} lnf_options;
+
+/*
+ * Create a filter context.  opt == NULL gives the defaults (LNF_MEAN9, gate off,
+ * current device).  Allocates only library-internal state (a few KB of device
+ * memory for the batch descriptor table and the histogram scratch).
+ * Errors: LNF_EINVAL (h NULL, bad rule/flags/size), LNF_EDEVICE (bad device),
+ * LNF_ENOMEM, LNF_EHIP.
+ */
+LNF_API int lnf_create(lnf_handle* h, const lnf_options* opt);
+
+/* Release a context's internal state; never touches caller buffers.  NULL is a no-op. */
+LNF_API int lnf_destroy(lnf_handle h);
+
+/*
+ * Filter one volume: out = filter(vol) with the context's rule and gate.
+ *   vol, out  device pointers on the context's device, same dtype and dims,
+ *             non-overlapping (the filter is a stencil); owned by the caller,
+ *             not retained after the call's work completes on `stream`.
+ *   dims      {nx, ny, nz}, each >= 1, nx*ny < 2^31.
+ *   dtype     LNF_U8 or LNF_U16.
+ *   radius    r in [1, LNF_RADIUS_MAX]; cluster side M = 2r+1.
+ *   stream    HIP stream the work is enqueued on (0 = null stream).
+ * Errors: LNF_EINVAL, LNF_EDEVICE, LNF_EHIP.
+ */
+LNF_API int lnf_filter(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                       int radius, void* out, hipStream_t stream);
+
+/*
+ * Tile configuration of the single-volume kernels.  Every configuration gives
+ * byte-identical output; they differ only in speed.
+ *   variant  index of a compiled tile shape (0 .. lnf_tile_variants()-1);
+ *            -1 = the context's tuned/default choice.
+ *   zs       z-strip depth (output slices per workgroup); 0 = default.
+ */
+typedef struct {
+    int32_t variant;
+    int32_t zs;
+} lnf_tile;
+
+/* Number of compiled tile shapes for (rule, dtype, radius); < 0 on bad arguments. */
+LNF_API int lnf_tile_variants(int rule, int dtype, int radius);
+
+/* lnf_filter with an explicit tile configuration (tile == NULL: as lnf_filter). */
+LNF_API int lnf_filter_tiled(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                             int radius, void* out, hipStream_t stream, const lnf_tile* tile);
+
+/* Human-readable text of a status code (static storage). */
+LNF_API const char* lnf_strerror(int code);
+
+/* ABI version: major*10000 + minor*100 + patch. */
+LNF_API int lnf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LNF_H */

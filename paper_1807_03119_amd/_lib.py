@@ -1,0 +1,174 @@
+"""ctypes binding of liblnf.so (include/lnf.h).
+
+Argument marshalling only: every step of the filter runs in the HIP library.
+Functions keep the C names; tensors are passed as device pointers and the
+current torch stream is used unless a stream is given.  There is no CPU
+fallback: if the library is missing, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblnf.so")
+
+LNF_OK = 0
+LNF_EINVAL = -1
+LNF_EDEVICE = -2
+LNF_ENOMEM = -3
+LNF_EHIP = -4
+LNF_EBUSY = -5
+LNF_ENOTFOUND = -6
+LNF_ECANCELED = -7
+LNF_ETIMEDOUT = -8
+
+LNF_U8 = 1
+LNF_U16 = 2
+LNF_MEAN9 = 0
+LNF_MINVAR9 = 1
+LNF_RADIUS_MAX = 4
+
+
+class LnfError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+class lnf_options(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("rule", ctypes.c_int32), ("gate_T", ctypes.c_uint32),
+                ("device", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class lnf_tile(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("zs", ctypes.c_int32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int
+_dims_t = ctypes.c_int64 * 3
+
+
+def _declare(lib):
+    sig = {
+        "lnf_create": [ctypes.POINTER(_vp), ctypes.POINTER(lnf_options)],
+        "lnf_destroy": [_vp],
+        "lnf_filter": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, _vp, _vp],
+        "lnf_filter_tiled": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, _vp, _vp,
+                             ctypes.POINTER(lnf_tile)],
+        "lnf_tile_variants": [_i32, _i32, _i32],
+        "lnf_version": [],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.lnf_strerror.argtypes = [_i32]
+    lib.lnf_strerror.restype = ctypes.c_char_p
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1807_03119_amd.build` (needs hipcc)")
+        handle = ctypes.CDLL(LIB_PATH)
+        _declare(handle)
+        _lib = handle
+    return _lib
+
+
+def strerror(code: int) -> str:
+    if _lib is None and not os.path.exists(LIB_PATH):
+        return f"status {code}"
+    return lib().lnf_strerror(code).decode()
+
+
+def _check(code: int, where: str) -> int:
+    if code != LNF_OK:
+        raise LnfError(code, where)
+    return code
+
+
+# ---------------------------------------------------------------------------
+# tensor marshalling helpers
+# ---------------------------------------------------------------------------
+
+def dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.uint8:
+        return LNF_U8
+    if t.dtype == torch.uint16:
+        return LNF_U16
+    raise TypeError(f"volumes must be torch.uint8 or torch.uint16, got {t.dtype}")
+
+
+def dims_of(t):
+    """(nx, ny, nz) of a contiguous [z, y, x] tensor."""
+    if t.dim() != 3:
+        raise ValueError("volumes are 3D tensors indexed [z, y, x]")
+    if not t.is_contiguous():
+        raise ValueError("volumes must be contiguous (x fastest)")
+    nz, ny, nx = t.shape
+    return (int(nx), int(ny), int(nz))
+
+
+def stream_ptr(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# C functions under their C names
+# ---------------------------------------------------------------------------
+
+def lnf_version() -> int:
+    return lib().lnf_version()
+
+
+def lnf_strerror(code: int) -> str:
+    return strerror(code)
+
+
+def lnf_create(rule: int = LNF_MEAN9, gate_T: int = 0, device: int = -1, flags: int = 0):
+    opt = lnf_options(ctypes.sizeof(lnf_options), rule, gate_T, device, flags)
+    h = _vp()
+    _check(lib().lnf_create(ctypes.byref(h), ctypes.byref(opt)), "lnf_create")
+    return h
+
+
+def lnf_destroy(h) -> None:
+    _check(lib().lnf_destroy(h), "lnf_destroy")
+
+
+def lnf_tile_variants(rule: int, dtype: int, radius: int) -> int:
+    n = lib().lnf_tile_variants(rule, dtype, radius)
+    if n < 0:
+        raise LnfError(n, "lnf_tile_variants")
+    return n
+
+
+def lnf_filter(h, vol, dims, dtype: int, radius: int, out, stream=None) -> int:
+    """C signature; `vol`/`out` are tensors or raw device addresses (ints)."""
+    vp = vol if isinstance(vol, int) else vol.data_ptr()
+    op = out if isinstance(out, int) else out.data_ptr()
+    d = _dims_t(*[int(v) for v in dims])
+    return lib().lnf_filter(h, vp, d, dtype, radius, op, stream_ptr(stream))
+
+
+def lnf_filter_tiled(h, vol, dims, dtype: int, radius: int, out, stream=None, variant: int = -1,
+                     zs: int = 0) -> int:
+    vp = vol if isinstance(vol, int) else vol.data_ptr()
+    op = out if isinstance(out, int) else out.data_ptr()
+    d = _dims_t(*[int(v) for v in dims])
+    t = lnf_tile(variant, zs)
+    return lib().lnf_filter_tiled(h, vp, d, dtype, radius, op, stream_ptr(stream),
+                                  ctypes.byref(t))

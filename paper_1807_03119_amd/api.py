@@ -1,0 +1,75 @@
+"""Tensor-level convenience layer over the C ABI (argument marshalling only).
+
+    from paper_1807_03119_amd.api import Filter
+    f = Filter(rule=LNF_MEAN9, gate=0)
+    out = f(vol_gpu_uint16, radius=3)          # torch tensor [z, y, x] on cuda
+
+Volumes are contiguous ``[z, y, x]`` torch tensors of dtype uint8 or uint16 on
+the context's device.  The work is enqueued on the current torch stream.
+"""
+from __future__ import annotations
+
+from . import _lib
+from ._lib import LNF_MEAN9, LNF_MINVAR9, LnfError  # noqa: F401
+
+
+def _require_cuda(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor (the filter runs only on the GPU)")
+
+
+class Filter:
+    """One lnf context: a rule and a gate threshold on one device."""
+
+    def __init__(self, rule: int = LNF_MEAN9, gate: int = 0, device: int | None = None):
+        import torch
+        dev = torch.cuda.current_device() if device is None else int(device)
+        self.rule, self.gate, self.device = rule, int(gate), dev
+        self._h = _lib.lnf_create(rule, int(gate), dev)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __call__(self, vol, radius: int, out=None, stream=None, variant: int = -1, zs: int = 0):
+        import torch
+        _require_cuda(vol, "vol")
+        dt = _lib.dtype_code(vol)
+        dims = _lib.dims_of(vol)
+        if out is None:
+            out = torch.empty_like(vol)
+        _require_cuda(out, "out")
+        rc = _lib.lnf_filter_tiled(self._h, vol, dims, dt, int(radius), out, stream,
+                                   variant=variant, zs=zs)
+        if rc != _lib.LNF_OK:
+            raise LnfError(rc, "lnf_filter")
+        return out
+
+    def close(self):
+        if self._h is not None:
+            _lib.lnf_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_cache: dict = {}
+
+
+def filter_volume(vol, radius: int, rule: int = LNF_MEAN9, gate: int = 0, out=None, stream=None):
+    """Filter one device volume with a cached context for (rule, gate, device)."""
+    key = (rule, int(gate), vol.device.index)
+    f = _cache.get(key)
+    if f is None:
+        f = _cache[key] = Filter(rule, gate, vol.device.index)
+    return f(vol, radius, out=out, stream=stream)

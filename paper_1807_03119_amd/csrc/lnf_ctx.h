@@ -1,0 +1,55 @@
+// Context state behind an lnf_handle, and host helpers shared by the C-ABI
+// translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <unordered_map>
+
+#include "lnf.h"
+#include "lnf_internal.h"
+
+namespace lnf {
+
+using TuneKey = uint64_t;
+TuneKey tune_key(int rule, int dtype, int radius, Geom g);
+
+}  // namespace lnf
+
+struct lnf_ctx {
+    int device = 0;
+    int rule = LNF_MEAN9;
+    uint32_t gate = 0;
+    mutable std::mutex mu;  // guards `tuned`
+    std::unordered_map<lnf::TuneKey, lnf::TileCfg> tuned;
+    void* dev_state = nullptr;  // library-internal device memory (see ctx_init_device_state)
+};
+
+namespace lnf {
+
+class DeviceGuard {
+public:
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+    bool ok() const { return ok_; }
+
+private:
+    int prev_ = -1;
+    bool ok_ = true;
+    bool switched_ = false;
+};
+
+int check_volume_args(const lnf_ctx* h, const void* vol, const int64_t dims[3], int dtype,
+                      int radius, const void* out, Geom* g, size_t* bytes);
+int check_device_range(const void* p, size_t bytes, int device);
+TileCfg ctx_tile(const lnf_ctx* h, int rule, int dtype, int radius, Geom g);
+hipError_t launch_rule(int rule, const void* in, void* out, int dtype, int r, Geom g,
+                       uint32_t gate, TileCfg cfg, hipStream_t s);
+
+// Allocate / release the context's internal device memory.
+int ctx_init_device_state(lnf_ctx* c);
+void ctx_free_device_state(lnf_ctx* c);
+
+}  // namespace lnf

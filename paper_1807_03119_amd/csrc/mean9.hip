@@ -1,0 +1,238 @@
+// MEAN9: every voxel becomes the rounded mean of its nine cluster means
+// (paper, Section "Our Method", eqs. 2-3 and the nine-cluster figure).
+//
+// The nine clusters have equal size n = (2r+1)^3, so the mean of means is
+// S / (9n) with S the sum over all nine clusters.  S is a convolution of the
+// clamp-extended volume E with a kernel that splits into two separable parts:
+//   S = box_x box_y box_z E  +  c_x c_y c_z E,
+//   box = ones on [-r, r]   (the centre cluster S_0),
+//   c   = ones on [-2r, 2r] plus one more at 0  (per axis, the two diagonal
+//         clusters at -r and +r overlap on the centre voxel; the product over
+//         the three axes enumerates the eight diagonal clusters).
+// The kernel evaluates it as separable running sums in exact uint32
+// arithmetic: per z-slice an x-pass and a y-pass through LDS, then a z-window
+// that slides through a register ring while the workgroup streams down its
+// z-strip.
+#include "device_common.h"
+#include "lnf_internal.h"
+
+namespace lnf {
+namespace {
+
+constexpr int kThreads = 256;
+
+// Output tile 64 (x) x 16 (y) per workgroup, streaming `zs` slices in z.
+// Per input slice:
+//   1. the raw (64+4r) x (16+4r) slice tile (clamped at the volume faces) is
+//      written from registers into LDS, and the next slice's loads are issued;
+//   2. x-pass: 8-wide row segments, prefix sums over the 8+4r raw values give
+//      px = box_x E and qx = c_x E for the 16+4r rows;
+//   3. y-pass: each thread owns one column x and four consecutive rows and
+//      forms P = box_y px and Q = c_y qx from prefix sums over the column;
+//   4. z-window: a ring of the last 4r+2 (P, Q) slices in registers keeps the
+//      running sums B = box_z P (lagging 2r slices) and W = sum of Q over
+//      [-2r, 2r]; the output slice z = zi - 2r is S = B + W + Q(z).
+template <int R, typename T, bool GATE>
+__global__ __launch_bounds__(kThreads) void mean9_ring_64x16(const T* __restrict__ in,
+                                                             T* __restrict__ out, Geom g, int zs,
+                                                             int tiles_x, int tiles_y, int total,
+                                                             uint32_t gate, double inv9n)
+{
+    constexpr int TX = 64, TY = 16, H = 2 * R;
+    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
+    constexpr int NRAW = LX * LY;
+    constexpr int NLOAD = (NRAW + kThreads - 1) / kThreads;
+    constexpr int NFULL = NRAW / kThreads;
+    constexpr int D = 4 * R + 2;  // ring period (slices kept per output column)
+    constexpr int SEG = 8, NSEG = TX / SEG, SW = SEG + 4 * R;
+    constexpr int YO = 4;  // outputs per thread along y
+    constexpr int NPV = YO + 2 * R, NQV = YO + 4 * R;
+    static_assert(LY * NSEG <= kThreads, "x-pass needs one thread per row segment");
+    static_assert(TX * (TY / YO) == kThreads, "y-pass needs one thread per column quad");
+
+    __shared__ __align__(16) uint32_t s_raw[LY * LX];
+    __shared__ __align__(16) uint32_t s_px[LY * TX];
+    __shared__ __align__(16) uint32_t s_qx[LY * TX];
+
+    const int tid = threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, total);
+    const int bx = tile % tiles_x;
+    const int rest = tile / tiles_x;
+    const int by = rest % tiles_y;
+    const int bz = rest / tiles_y;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * zs;
+    const int z1 = min(z0 + zs, g.nz);
+    const size_t plane = (size_t)g.nx * g.ny;
+
+    // In-slice offsets of the raw elements this thread stages (clamped).
+    int off[NLOAD];
+#pragma unroll
+    for (int i = 0; i < NLOAD; ++i) {
+        const int e = min(tid + i * kThreads, NRAW - 1);
+        const int row = e / LX, col = e - row * LX;
+        const int gy = clampi(y0 - H + row, 0, g.ny - 1);
+        const int gx = clampi(x0 - H + col, 0, g.nx - 1);
+        off[i] = gy * g.nx + gx;
+    }
+    const bool last_ok = tid + (NLOAD - 1) * kThreads < NRAW;
+
+    uint32_t v[NLOAD];
+    auto load = [&](int zi) {
+        const T* base = in + (size_t)clampi(zi, 0, g.nz - 1) * plane;
+#pragma unroll
+        for (int i = 0; i < NLOAD; ++i) v[i] = base[off[i]];
+    };
+
+    const int xrow = tid / NSEG, xseg = tid % NSEG;
+    const bool xactive = xrow < LY;
+    const int xq = tid % TX, yg = tid / TX;
+
+    uint32_t pr[D][YO], qr[D][YO], bacc[YO], wacc[YO];
+#pragma unroll
+    for (int m = 0; m < YO; ++m) {
+        bacc[m] = wacc[m] = 0;
+#pragma unroll
+        for (int u = 0; u < D; ++u) pr[u][m] = qr[u][m] = 0;
+    }
+
+    const int ns = (z1 - z0) + 2 * H;  // input slices z0-2r .. z1-1+2r
+    load(z0 - H);
+    for (int kb = 0; kb < ns; kb += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int k = kb + u;
+            if (k >= ns) break;
+            // 1. stage slice k, prefetch slice k+1
+#pragma unroll
+            for (int i = 0; i < NLOAD; ++i)
+                if (i < NFULL || last_ok) s_raw[tid + i * kThreads] = v[i];
+            if (k + 1 < ns) load(z0 - H + k + 1);
+            __syncthreads();
+
+            // 2. x-pass
+            if (xactive) {
+                uint32_t w[SW], c[SW];
+                const uint32_t* rp = s_raw + xrow * LX + xseg * SEG;
+#pragma unroll
+                for (int i = 0; i < SW; i += 4) {
+                    const uint4 t4 = *reinterpret_cast<const uint4*>(rp + i);
+                    w[i] = t4.x;
+                    w[i + 1] = t4.y;
+                    w[i + 2] = t4.z;
+                    w[i + 3] = t4.w;
+                }
+                c[0] = w[0];
+#pragma unroll
+                for (int i = 1; i < SW; ++i) c[i] = c[i - 1] + w[i];
+                uint32_t pp[SEG], qq[SEG];
+#pragma unroll
+                for (int m = 0; m < SEG; ++m) {
+                    qq[m] = c[m + 4 * R] - (m ? c[m - 1] : 0u) + w[m + 2 * R];
+                    pp[m] = c[m + 3 * R] - c[m + R - 1];
+                }
+                uint32_t* pd = s_px + xrow * TX + xseg * SEG;
+                uint32_t* qd = s_qx + xrow * TX + xseg * SEG;
+#pragma unroll
+                for (int m = 0; m < SEG; m += 4) {
+                    *reinterpret_cast<uint4*>(pd + m) = make_uint4(pp[m], pp[m + 1], pp[m + 2], pp[m + 3]);
+                    *reinterpret_cast<uint4*>(qd + m) = make_uint4(qq[m], qq[m + 1], qq[m + 2], qq[m + 3]);
+                }
+            }
+            __syncthreads();
+
+            // 3. y-pass for rows yg*4 .. yg*4+3 of column xq
+            uint32_t cp[NPV], cq[NQV], qc[YO];
+            cp[0] = s_px[(yg * YO + R) * TX + xq];
+#pragma unroll
+            for (int i = 1; i < NPV; ++i) cp[i] = cp[i - 1] + s_px[(yg * YO + R + i) * TX + xq];
+            {
+                uint32_t qv[NQV];
+#pragma unroll
+                for (int i = 0; i < NQV; ++i) qv[i] = s_qx[(yg * YO + i) * TX + xq];
+                cq[0] = qv[0];
+#pragma unroll
+                for (int i = 1; i < NQV; ++i) cq[i] = cq[i - 1] + qv[i];
+#pragma unroll
+                for (int m = 0; m < YO; ++m) qc[m] = qv[m + 2 * R];
+            }
+
+            // 4. z-window over the register ring
+#pragma unroll
+            for (int m = 0; m < YO; ++m) {
+                const uint32_t P = cp[m + 2 * R] - (m ? cp[m - 1] : 0u);
+                const uint32_t Q = cq[m + 4 * R] - (m ? cq[m - 1] : 0u) + qc[m];
+                bacc[m] += pr[(u + D - R) % D][m] - pr[(u + R + 1) % D][m];
+                wacc[m] += Q - qr[(u + 1) % D][m];
+                pr[u][m] = P;
+                qr[u][m] = Q;
+            }
+            if (k >= 2 * H) {
+                const int z = z0 + k - 2 * H;
+                T* op = out + (size_t)z * plane;
+                const int x = x0 + xq;
+#pragma unroll
+                for (int m = 0; m < YO; ++m) {
+                    const uint32_t S = bacc[m] + wacc[m] + qr[(u + D - 2 * R) % D][m];
+                    uint32_t o = round_div_odd(S, inv9n);
+                    if (GATE && o < gate) o = 0;
+                    const int y = y0 + yg * YO + m;
+                    if (x < g.nx && y < g.ny) op[(size_t)y * g.nx + x] = (T)o;
+                }
+            }
+        }
+    }
+}
+
+template <int R, typename T>
+hipError_t launch_ring_64x16(const void* in, void* out, Geom g, uint32_t gate, int zs,
+                             hipStream_t s)
+{
+    const int tiles_x = (g.nx + 63) / 64, tiles_y = (g.ny + 15) / 16;
+    if (zs <= 0) zs = default_zs(tiles_x * tiles_y, g.nz, 1024);
+    const int nzs = (g.nz + zs - 1) / zs;
+    const int total = tiles_x * tiles_y * nzs;
+    const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
+    const double inv9n = 1.0 / (9.0 * n);
+    const T* pin = static_cast<const T*>(in);
+    T* pout = static_cast<T*>(out);
+    if (gate)
+        hipLaunchKernelGGL((mean9_ring_64x16<R, T, true>), dim3(total), dim3(kThreads), 0, s,
+                           pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
+    else
+        hipLaunchKernelGGL((mean9_ring_64x16<R, T, false>), dim3(total), dim3(kThreads), 0, s,
+                           pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_r(const void* in, void* out, int r, Geom g, uint32_t gate, TileCfg cfg,
+                      hipStream_t s)
+{
+    switch (r) {
+    case 1: return launch_ring_64x16<1, T>(in, out, g, gate, cfg.zs, s);
+    case 2: return launch_ring_64x16<2, T>(in, out, g, gate, cfg.zs, s);
+    case 3: return launch_ring_64x16<3, T>(in, out, g, gate, cfg.zs, s);
+    case 4: return launch_ring_64x16<4, T>(in, out, g, gate, cfg.zs, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int mean9_variants() { return 1; }
+
+void mean9_tile_shape(int variant, int* tx, int* ty)
+{
+    (void)variant;
+    *tx = 64;
+    *ty = 16;
+}
+
+hipError_t launch_mean9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
+                        TileCfg cfg, hipStream_t s)
+{
+    if (dtype == LNF_U8) return dispatch_r<uint8_t>(in, out, r, g, gate, cfg, s);
+    return dispatch_r<uint16_t>(in, out, r, g, gate, cfg, s);
+}
+
+}  // namespace lnf

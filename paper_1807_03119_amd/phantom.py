@@ -6,8 +6,9 @@ The paper evaluates its filter on an SRuCT scan of a tachinid fly (Section
 stand in for it: random ellipsoids and tubes of constant grey value on a
 constant background, plus additive noise, rounded and clipped to the bit depth
 of the volume.  This module holds no part of the filter's arithmetic; it only
-draws numbers from numpy's PCG64 generator in a fixed order, so that a seed
-fixes every byte.
+draws numbers from numpy's PCG64 generator (and, for the large volumes built on
+the GPU, torch's device generator) in a fixed order, so that a seed fixes every
+byte.
 
 Volumes are numpy arrays indexed ``[z, y, x]`` (x fastest), matching the
 device layout.  Dimensions are always quoted as ``(nx, ny, nz)``.
@@ -117,22 +118,12 @@ def phantom(dims, spec: PhantomSpec, seed: int, noise_slab: int = 32) -> np.ndar
     """
     nx, ny, nz = (int(d) for d in dims)
     rng = np.random.default_rng(seed)
-    ref = float(min(nx, ny, nz))
     clean = np.full((nz, ny, nx), spec.background * spec.scale, dtype=np.int32)
-    for _ in range(spec.n_ellipsoids):
-        c = rng.uniform(0.2, 0.8, 3) * np.array([nx, ny, nz], dtype=np.float64)
-        semi = rng.uniform(0.05, 0.3, 3) * ref
-        rot = _rotation(rng)
-        val = int(rng.integers(spec.lo, spec.hi + 1)) * spec.scale
-        _paint_ellipsoid(clean, c, semi, rot, val)
-    for _ in range(spec.n_cylinders):
-        c = rng.uniform(0.2, 0.8, 3) * np.array([nx, ny, nz], dtype=np.float64)
-        ax = rng.standard_normal(3)
-        ax = ax / np.linalg.norm(ax)
-        rad = float(rng.uniform(0.01, 0.04)) * ref
-        half = float(rng.uniform(0.1, 0.4)) * ref
-        val = int(rng.integers(spec.lo, spec.hi + 1)) * spec.scale
-        _paint_cylinder(clean, c, ax, rad, half, val)
+    for sh in _shape_params((nx, ny, nz), spec, rng):
+        if sh[0] == "ellipsoid":
+            _paint_ellipsoid(clean, *sh[1:])
+        else:
+            _paint_cylinder(clean, *sh[1:])
     out = np.empty((nz, ny, nx), dtype=spec.dtype)
     for z0 in range(0, nz, noise_slab):
         z1 = min(nz, z0 + noise_slab)
@@ -148,6 +139,82 @@ def phantom(dims, spec: PhantomSpec, seed: int, noise_slab: int = 32) -> np.ndar
     return out
 
 
+def _shape_params(dims, spec: PhantomSpec, rng: np.random.Generator):
+    """Draw every shape of the phantom, in the order `phantom` documents."""
+    nx, ny, nz = dims
+    ref = float(min(nx, ny, nz))
+    shapes = []
+    for _ in range(spec.n_ellipsoids):
+        c = rng.uniform(0.2, 0.8, 3) * np.array([nx, ny, nz], dtype=np.float64)
+        semi = rng.uniform(0.05, 0.3, 3) * ref
+        rot = _rotation(rng)
+        val = int(rng.integers(spec.lo, spec.hi + 1)) * spec.scale
+        shapes.append(("ellipsoid", c, semi, rot, val))
+    for _ in range(spec.n_cylinders):
+        c = rng.uniform(0.2, 0.8, 3) * np.array([nx, ny, nz], dtype=np.float64)
+        ax = rng.standard_normal(3)
+        ax = ax / np.linalg.norm(ax)
+        rad = float(rng.uniform(0.01, 0.04)) * ref
+        half = float(rng.uniform(0.1, 0.4)) * ref
+        val = int(rng.integers(spec.lo, spec.hi + 1)) * spec.scale
+        shapes.append(("cylinder", c, ax, rad, half, val))
+    return shapes
+
+
+def phantom_device(dims, spec: PhantomSpec, seed: int, device, slab: int = 64):
+    """The same recipe as `phantom`, rasterised and noised on a torch device.
+
+    Shape parameters come from numpy's PCG64 (same draws as `phantom`); the
+    noise field comes from torch's generator on `device` seeded with `seed`,
+    drawn in z-slabs of `slab` slices, in float32.  Used for the large volumes,
+    whose numpy generation would take minutes.  Returns a [z, y, x] tensor.
+    """
+    import torch
+    nx, ny, nz = (int(d) for d in dims)
+    rng = np.random.default_rng(seed)
+    shapes = _shape_params((nx, ny, nz), spec, rng)
+    tdt = torch.uint8 if spec.dtype == np.uint8 else torch.uint16
+    out = torch.empty((nz, ny, nx), dtype=tdt, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    f64 = torch.float64
+    xs = torch.arange(nx, device=device, dtype=f64)
+    ys = torch.arange(ny, device=device, dtype=f64)
+    for z0 in range(0, nz, slab):
+        z1 = min(nz, z0 + slab)
+        zs = torch.arange(z0, z1, device=device, dtype=f64)
+        clean = torch.full((z1 - z0, ny, nx), float(spec.background * spec.scale),
+                           dtype=torch.float32, device=device)
+        for sh in shapes:
+            if sh[0] == "ellipsoid":
+                _, c, semi, rot, val = sh
+                a = rot @ np.diag(1.0 / np.asarray(semi) ** 2) @ rot.T
+                dx = (xs - c[0])[None, None, :]
+                dy = (ys - c[1])[None, :, None]
+                dz = (zs - c[2])[:, None, None]
+                lin = 2.0 * (float(a[0, 1]) * dy + float(a[0, 2]) * dz)
+                quad = float(a[1, 1]) * dy * dy + 2.0 * float(a[1, 2]) * dy * dz + \
+                    float(a[2, 2]) * dz * dz
+                q = dx * (float(a[0, 0]) * dx + lin) + quad
+                clean.masked_fill_(q <= 1.0, float(val))
+            else:
+                _, c, ax, rad, half, val = sh
+                dx = (xs - c[0])[None, None, :]
+                dy = (ys - c[1])[None, :, None]
+                dz = (zs - c[2])[:, None, None]
+                t = dx * float(ax[0]) + dy * float(ax[1]) + dz * float(ax[2])
+                d2 = dx * dx + dy * dy + dz * dz - t * t
+                clean.masked_fill_((t.abs() <= half) & (d2 <= rad * rad), float(val))
+        g = torch.randn(clean.shape, generator=gen, device=device, dtype=torch.float32)
+        if spec.noise == "gauss":
+            noisy = clean + spec.sigma * g
+        else:
+            noisy = clean + spec.sigma * torch.sqrt(clean) * g
+        noisy = torch.clamp(torch.round(noisy), 0, spec.vmax)
+        out[z0:z1] = noisy.to(torch.int32).to(tdt)
+    return out
+
+
 # --------------------------------------------------------------------------
 # workload presets
 # --------------------------------------------------------------------------
@@ -157,8 +224,12 @@ def small_u8(seed: int = 1000, dims=(64, 64, 64)) -> np.ndarray:
     return phantom(dims, SPEC_U8, seed)
 
 
-def ct_u12(dims=(512, 512, 512), seed: int = 2000) -> np.ndarray:
-    """uint16 holding 12-bit data: 40 ellipsoids + 20 tubes, sigma = 4*sqrt(value)."""
+def ct_u12(dims=(512, 512, 512), seed: int = 2000, device=None):
+    """uint16 holding 12-bit data: 40 ellipsoids + 20 tubes, sigma = 4*sqrt(value).
+
+    With `device` given, generated there by `phantom_device` (a torch tensor)."""
+    if device is not None:
+        return phantom_device(dims, SPEC_U12, seed, device)
     return phantom(dims, SPEC_U12, seed)
 
 
