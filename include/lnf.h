@@ -120,6 +120,45 @@ LNF_API int lnf_tile_variants(int rule, int dtype, int radius);
 LNF_API int lnf_filter_tiled(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
                              int radius, void* out, hipStream_t stream, const lnf_tile* tile);
 
+/* ---- batch ------------------------------------------------------------- */
+/* One volume of a batch.  Same contract as the arguments of lnf_filter. */
+typedef struct {
+    const void* in;      /* device input volume */
+    void* out;           /* device output volume: same dtype and dims, no overlap with any in */
+    int64_t dims[3];     /* {nx, ny, nz} */
+    int32_t dtype;       /* LNF_U8 or LNF_U16 */
+    int32_t radius;      /* 1 .. LNF_RADIUS_MAX */
+} lnf_job;
+
+#define LNF_BATCH_MAX 4096 /* most jobs one lnf_filter_batch call accepts */
+
+/*
+ * Filter n volumes with the context's rule and gate in ONE graph launch: the
+ * tiles of all jobs go to one persistent kernel per radius class, whose
+ * workgroups pull tiles from an atomic work queue until it is empty.  Each
+ * output is byte-identical to lnf_filter on the same job.  The job table is
+ * copied to the device by the graph itself, so `jobs` may be reused as soon as
+ * the call returns; the buffers must stay valid until the work completes on
+ * `stream`.  n == 0 is a no-op.
+ * Errors: LNF_EINVAL (n < 0 or > LNF_BATCH_MAX, a bad job, jobs whose outputs
+ * overlap any input or output), LNF_EDEVICE, LNF_ENOMEM, LNF_EHIP.  On error
+ * nothing is launched.
+ */
+LNF_API int lnf_filter_batch(lnf_handle h, const lnf_job* jobs, int n, hipStream_t stream);
+
+/*
+ * Autotune: for every distinct (dtype, radius, volume-size class) among the
+ * sample jobs, time each tile variant and z-strip depth on that job (its output
+ * is overwritten) and keep the fastest for later lnf_filter / lnf_filter_batch
+ * calls of this context.  Synchronous; uses an internal stream.
+ * Errors: as lnf_filter_batch.
+ */
+LNF_API int lnf_tune(lnf_handle h, const lnf_job* sample, int n);
+
+/* Write / read the context's tuned configurations (text, one per line). */
+LNF_API int lnf_tune_save(lnf_handle h, const char* path);
+LNF_API int lnf_tune_load(lnf_handle h, const char* path);
+
 /* Human-readable text of a status code (static storage). */
 LNF_API const char* lnf_strerror(int code);
 

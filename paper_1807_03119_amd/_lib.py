@@ -45,6 +45,15 @@ class lnf_tile(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("zs", ctypes.c_int32)]
 
 
+class lnf_job(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("dims", ctypes.c_int64 * 3), ("dtype", ctypes.c_int32),
+                ("radius", ctypes.c_int32)]
+
+
+LNF_BATCH_MAX = 4096
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int
@@ -59,6 +68,10 @@ def _declare(lib):
         "lnf_filter_tiled": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, _vp, _vp,
                              ctypes.POINTER(lnf_tile)],
         "lnf_tile_variants": [_i32, _i32, _i32],
+        "lnf_filter_batch": [_vp, ctypes.POINTER(lnf_job), _i32, _vp],
+        "lnf_tune": [_vp, ctypes.POINTER(lnf_job), _i32],
+        "lnf_tune_save": [_vp, ctypes.c_char_p],
+        "lnf_tune_load": [_vp, ctypes.c_char_p],
         "lnf_version": [],
     }
     for name, args in sig.items():
@@ -172,3 +185,48 @@ def lnf_filter_tiled(h, vol, dims, dtype: int, radius: int, out, stream=None, va
     t = lnf_tile(variant, zs)
     return lib().lnf_filter_tiled(h, vp, d, dtype, radius, op, stream_ptr(stream),
                                   ctypes.byref(t))
+
+
+def make_jobs(items):
+    """ctypes array of lnf_job from (vol, out, radius) triples of tensors (or
+    (in_ptr, out_ptr, dims, dtype, radius) tuples of raw values)."""
+    arr = (lnf_job * max(len(items), 1))()
+    for i, it in enumerate(items):
+        if len(it) == 3:
+            vol, out, r = it
+            arr[i].in_ = vol.data_ptr()
+            arr[i].out = out.data_ptr()
+            arr[i].dims = (ctypes.c_int64 * 3)(*dims_of(vol))
+            arr[i].dtype = dtype_code(vol)
+            arr[i].radius = int(r)
+        else:
+            ip, op, dims, dt, r = it
+            arr[i].in_, arr[i].out = int(ip), int(op)
+            arr[i].dims = (ctypes.c_int64 * 3)(*[int(d) for d in dims])
+            arr[i].dtype, arr[i].radius = int(dt), int(r)
+    return arr
+
+
+def lnf_filter_batch(h, jobs, n=None, stream=None) -> int:
+    """`jobs`: a make_jobs array (or a list accepted by make_jobs)."""
+    if isinstance(jobs, (list, tuple)):
+        n = len(jobs) if n is None else n
+        jobs = make_jobs(jobs)
+    n = len(jobs) if n is None else n
+    return lib().lnf_filter_batch(h, jobs, n, stream_ptr(stream))
+
+
+def lnf_tune(h, jobs, n=None) -> int:
+    if isinstance(jobs, (list, tuple)):
+        n = len(jobs) if n is None else n
+        jobs = make_jobs(jobs)
+    n = len(jobs) if n is None else n
+    return lib().lnf_tune(h, jobs, n)
+
+
+def lnf_tune_save(h, path: str) -> int:
+    return lib().lnf_tune_save(h, path.encode())
+
+
+def lnf_tune_load(h, path: str) -> int:
+    return lib().lnf_tune_load(h, path.encode())

@@ -45,6 +45,30 @@ class Filter:
             raise LnfError(rc, "lnf_filter")
         return out
 
+    def batch(self, items, stream=None):
+        """Filter [(vol, radius), ...] (or [(vol, out, radius), ...]) in one graph
+        launch; returns the list of outputs."""
+        import torch
+        triples = []
+        for it in items:
+            if len(it) == 2:
+                vol, r = it
+                out = torch.empty_like(vol)
+            else:
+                vol, out, r = it
+            _require_cuda(vol, "vol")
+            triples.append((vol, out, r))
+        rc = _lib.lnf_filter_batch(self._h, triples, stream=stream)
+        if rc != _lib.LNF_OK:
+            raise LnfError(rc, "lnf_filter_batch")
+        return [t[1] for t in triples]
+
+    def tune(self, items):
+        """Autotune on [(vol, out, radius), ...]; outputs are overwritten."""
+        rc = _lib.lnf_tune(self._h, list(items))
+        if rc != _lib.LNF_OK:
+            raise LnfError(rc, "lnf_tune")
+
     def close(self):
         if self._h is not None:
             _lib.lnf_destroy(self._h)

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -82,7 +83,7 @@ DeviceGuard::~DeviceGuard()
 
 TileCfg ctx_tile(const lnf_ctx* h, int rule, int dtype, int radius, Geom g)
 {
-    TileCfg cfg{0, 0};
+    TileCfg cfg{-1, 0};  // -1: the rule's default variant
     const TuneKey key = tune_key(rule, dtype, radius, g);
     std::lock_guard<std::mutex> lk(h->mu);
     auto it = h->tuned.find(key);
@@ -115,6 +116,7 @@ int ctx_init_device_state(lnf_ctx* c)
 
 void ctx_free_device_state(lnf_ctx* c)
 {
+    batch_state_free(c);
     c->dev_state = nullptr;
 }
 
@@ -171,6 +173,7 @@ int lnf_create(lnf_handle* h, const lnf_options* opt)
         delete c;
         return rc;
     }
+    if (const char* cache = std::getenv("LNF_TUNE_CACHE")) (void)lnf_tune_load(c, cache);
     *h = c;
     return LNF_OK;
 }
@@ -178,7 +181,10 @@ int lnf_create(lnf_handle* h, const lnf_options* opt)
 int lnf_destroy(lnf_handle h)
 {
     if (!h) return LNF_OK;
-    ctx_free_device_state(h);
+    {
+        DeviceGuard dg(h->device);
+        ctx_free_device_state(h);
+    }
     delete h;
     return LNF_OK;
 }

@@ -21,6 +21,66 @@ __device__ __forceinline__ int xcd_tile(int b, int total)
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// ---- buffer resources -------------------------------------------------------
+// A raw buffer resource holds a 64-bit base and a byte size in SGPRs, so the
+// per-lane address is a 32-bit byte offset (no 64-bit VALU address math), and
+// any access at or beyond `bytes` is dropped by the hardware.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+using lds_void_t = __attribute__((address_space(3))) void;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t buffer_load(rsrc_t r, uint32_t voff);
+template <>
+__device__ __forceinline__ uint32_t buffer_load<uint8_t>(rsrc_t r, uint32_t voff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b8(r, voff, 0, 0);
+}
+template <>
+__device__ __forceinline__ uint32_t buffer_load<uint16_t>(rsrc_t r, uint32_t voff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b16(r, voff, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ void buffer_store(uint32_t v, rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ void buffer_store<uint8_t>(uint32_t v, rsrc_t r, uint32_t voff,
+                                                      uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, r, voff, soff, 0);
+}
+template <>
+__device__ __forceinline__ void buffer_store<uint16_t>(uint32_t v, rsrc_t r, uint32_t voff,
+                                                       uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)v, r, voff, soff, 0);
+}
+
+// Direct buffer -> LDS load of one element per lane (LDS DMA).  The element is
+// zero-extended to 32 bits and written to LDS at dst + 4 * lane, where dst is
+// wave-uniform; the load bypasses VGPRs and completes asynchronously (vmcnt).
+template <typename T>
+__device__ __forceinline__ void buffer_load_lds(rsrc_t r, void* dst_wave, uint32_t voff);
+template <>
+__device__ __forceinline__ void buffer_load_lds<uint8_t>(rsrc_t r, void* dst_wave, uint32_t voff)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)dst_wave, 1, voff, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ void buffer_load_lds<uint16_t>(rsrc_t r, void* dst_wave, uint32_t voff)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)dst_wave, 2, voff, 0, 0, 0);
+}
+
+// Wait for this wave's outstanding vector-memory operations (including LDS DMA).
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // round(S / d) for an odd divisor d, as trunc(S * (1/d) + 1/2) in fp64.
 // (2S + d) / (2d) is never an integer (odd over even), so it lies at least
 // 1/(2d) from every integer, while the fp64 error is below 2^-52 * S/d; with

@@ -7,12 +7,14 @@
 #include <cstdint>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "lnf.h"
 #include "lnf_internal.h"
 
 namespace lnf {
 
+struct BatchState;  // batch.hip: staging slots and graphs of lnf_filter_batch
 using TuneKey = uint64_t;
 TuneKey tune_key(int rule, int dtype, int radius, Geom g);
 
@@ -25,6 +27,7 @@ struct lnf_ctx {
     mutable std::mutex mu;  // guards `tuned`
     std::unordered_map<lnf::TuneKey, lnf::TileCfg> tuned;
     void* dev_state = nullptr;  // library-internal device memory (see ctx_init_device_state)
+    lnf::BatchState* batch = nullptr;  // created on the first lnf_filter_batch call
 };
 
 namespace lnf {
@@ -47,6 +50,10 @@ int check_device_range(const void* p, size_t bytes, int device);
 TileCfg ctx_tile(const lnf_ctx* h, int rule, int dtype, int radius, Geom g);
 hipError_t launch_rule(int rule, const void* in, void* out, int dtype, int r, Geom g,
                        uint32_t gate, TileCfg cfg, hipStream_t s);
+
+// Batch path (batch.hip).
+int validate_jobs(const lnf_ctx* h, const lnf_job* jobs, int n, std::vector<Geom>* geoms);
+void batch_state_free(lnf_ctx* h);
 
 // Allocate / release the context's internal device memory.
 int ctx_init_device_state(lnf_ctx* c);

@@ -25,6 +25,7 @@ struct TileCfg {
 
 // ---- MEAN9 (mean of the nine cluster means) -------------------------------
 int mean9_variants();
+int mean9_default_variant();
 // Tile footprint of a variant: output tile width/height in x/y.
 void mean9_tile_shape(int variant, int* tx, int* ty);
 hipError_t launch_mean9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,

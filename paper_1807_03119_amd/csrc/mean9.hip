@@ -15,6 +15,7 @@
 // z-strip.
 #include "device_common.h"
 #include "lnf_internal.h"
+#include "mean9_tile.h"
 
 namespace lnf {
 namespace {
@@ -183,49 +184,95 @@ __global__ __launch_bounds__(kThreads) void mean9_ring_64x16(const T* __restrict
     }
 }
 
-template <int R, typename T>
-hipError_t launch_ring_64x16(const void* in, void* out, Geom g, uint32_t gate, int zs,
-                             hipStream_t s)
+// Single-volume wrapper around the streaming tile body of mean9_tile.h.
+template <int R, int TY, typename T, bool GATE>
+__global__ __launch_bounds__((M9Shape<R, TY>::THREADS)) void mean9_stream(
+    const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
+    int total, uint32_t gate, double inv9n)
 {
-    const int tiles_x = (g.nx + 63) / 64, tiles_y = (g.ny + 15) / 16;
-    if (zs <= 0) zs = default_zs(tiles_x * tiles_y, g.nz, 1024);
+    __shared__ __align__(16) M9Smem<R, TY> sm;
+    const int tile = xcd_tile(blockIdx.x, total);
+    const int bx = tile % tiles_x;
+    const int rest = tile / tiles_x;
+    const int by = rest % tiles_y;
+    const int bz = rest / tiles_y;
+    const int z0 = bz * zs;
+    mean9_tile<R, TY, T, GATE>(sm, in, out, g, bx * 64, by * TY, z0, min(z0 + zs, g.nz), gate,
+                               inv9n);
+}
+
+struct Variant {
+    int tx, ty, threads;
+    int target_groups;  // default z-strip depth aims at this many workgroups
+};
+// 0: first design (two barriers per slice, register staging)
+// 1, 2: LDS-DMA staging, double buffering, one barrier per slice
+constexpr Variant kVariants[] = {{64, 16, 256, 1024}, {64, 16, 256, 1024}, {64, 32, 512, 512}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+constexpr int kDefaultVariant = 1;
+
+template <int R, typename T, bool GATE>
+hipError_t launch_variant(int variant, const void* in, void* out, Geom g, uint32_t gate, int zs,
+                          hipStream_t s)
+{
+    const Variant v = kVariants[variant];
+    const int tiles_x = (g.nx + v.tx - 1) / v.tx, tiles_y = (g.ny + v.ty - 1) / v.ty;
+    if (zs <= 0) zs = default_zs(tiles_x * tiles_y, g.nz, v.target_groups);
     const int nzs = (g.nz + zs - 1) / zs;
     const int total = tiles_x * tiles_y * nzs;
     const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
     const double inv9n = 1.0 / (9.0 * n);
     const T* pin = static_cast<const T*>(in);
     T* pout = static_cast<T*>(out);
-    if (gate)
-        hipLaunchKernelGGL((mean9_ring_64x16<R, T, true>), dim3(total), dim3(kThreads), 0, s,
+    switch (variant) {
+    case 0:
+        hipLaunchKernelGGL((mean9_ring_64x16<R, T, GATE>), dim3(total), dim3(v.threads), 0, s,
                            pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
-    else
-        hipLaunchKernelGGL((mean9_ring_64x16<R, T, false>), dim3(total), dim3(kThreads), 0, s,
+        break;
+    case 1:
+        hipLaunchKernelGGL((mean9_stream<R, 16, T, GATE>), dim3(total), dim3(v.threads), 0, s,
                            pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
+        break;
+    default:
+        hipLaunchKernelGGL((mean9_stream<R, 32, T, GATE>), dim3(total), dim3(v.threads), 0, s,
+                           pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
+        break;
+    }
     return hipGetLastError();
+}
+
+template <int R, typename T>
+hipError_t launch_r(int variant, const void* in, void* out, Geom g, uint32_t gate, int zs,
+                    hipStream_t s)
+{
+    if (gate) return launch_variant<R, T, true>(variant, in, out, g, gate, zs, s);
+    return launch_variant<R, T, false>(variant, in, out, g, gate, zs, s);
 }
 
 template <typename T>
 hipError_t dispatch_r(const void* in, void* out, int r, Geom g, uint32_t gate, TileCfg cfg,
                       hipStream_t s)
 {
+    const int v = (cfg.variant >= 0 && cfg.variant < kNumVariants) ? cfg.variant : kDefaultVariant;
     switch (r) {
-    case 1: return launch_ring_64x16<1, T>(in, out, g, gate, cfg.zs, s);
-    case 2: return launch_ring_64x16<2, T>(in, out, g, gate, cfg.zs, s);
-    case 3: return launch_ring_64x16<3, T>(in, out, g, gate, cfg.zs, s);
-    case 4: return launch_ring_64x16<4, T>(in, out, g, gate, cfg.zs, s);
+    case 1: return launch_r<1, T>(v, in, out, g, gate, cfg.zs, s);
+    case 2: return launch_r<2, T>(v, in, out, g, gate, cfg.zs, s);
+    case 3: return launch_r<3, T>(v, in, out, g, gate, cfg.zs, s);
+    case 4: return launch_r<4, T>(v, in, out, g, gate, cfg.zs, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-int mean9_variants() { return 1; }
+int mean9_variants() { return kNumVariants; }
+int mean9_default_variant() { return kDefaultVariant; }
 
 void mean9_tile_shape(int variant, int* tx, int* ty)
 {
-    (void)variant;
-    *tx = 64;
-    *ty = 16;
+    const Variant v = kVariants[(variant >= 0 && variant < kNumVariants) ? variant : kDefaultVariant];
+    *tx = v.tx;
+    *ty = v.ty;
 }
 
 hipError_t launch_mean9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,

@@ -1,0 +1,200 @@
+// Streaming MEAN9 tile body: one workgroup filters a 64 x TY column of output
+// voxels over the z-range [z0, z1).  Shared by the single-volume kernel and the
+// persistent batch kernel.
+//
+// Arithmetic (paper, Section "Our Method", eqs. 2-3): the sum S over the nine
+// clusters is box_x box_y box_z E + c_x c_y c_z E, with box = ones on [-r, r]
+// and c = ones on [-2r, 2r] plus one more at the centre (the two diagonal
+// clusters of an axis overlap there).  Everything is exact uint32.
+//
+// Pipeline per input slice k (one barrier per slice; stages listed in the
+// order they are issued within one iteration):
+//   - LDS DMA: the raw (64+4r) x (TY+4r) tile of slice k+1 is loaded straight
+//     from HBM into LDS (one element per lane, zero-extended to 32 bits), its
+//     coordinates clamped into the volume per lane;
+//   - x-pass of slice k: each thread takes an 8-wide row segment, forms prefix
+//     sums over its 8+4r raw values and writes px = box_x E and qx = c_x E;
+//   - y-pass of slice k-1: each thread owns one column and four rows, forms
+//     P = box_y px and Q = c_y qx from prefix sums, and pushes them into a
+//     register ring of the last 4r+2 slices; the ring keeps the running sums
+//     B = sum of P over [z-r, z+r] and W = sum of Q over [z-2r, z+2r] for the
+//     output slice z, two r behind the newest slice, and S = B + W + Q(z);
+//   - out = round(S / 9n) (fp64, exact), gate, store.
+// raw, px and qx are double-buffered, so the x-pass of slice k overlaps the
+// y-pass of slice k-1 and the DMA of slice k+1.
+#pragma once
+
+#include "device_common.h"
+#include "lnf_internal.h"
+
+namespace lnf {
+
+template <int R, int TY>
+struct M9Shape {
+    static constexpr int TX = 64;
+    static constexpr int YO = 4;                    // output rows per thread
+    static constexpr int THREADS = TX * TY / YO;    // one thread per column x YO rows
+    static constexpr int H = 2 * R;                 // halo: cluster radius + offset
+    static constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
+    static constexpr int NRAW = LX * LY;
+    static constexpr int NLOAD = (NRAW + THREADS - 1) / THREADS;
+    static constexpr int NFULL = NRAW / THREADS;
+    static constexpr int PXP = TX + 4;              // padded px/qx row pitch (words)
+    static constexpr int D = 4 * R + 2;             // ring period (even)
+    static constexpr int SEG = 8, NSEG = TX / SEG, SW = SEG + 4 * R;
+    static constexpr int NPV = YO + 2 * R, NQV = YO + 4 * R;
+    static_assert(LY * NSEG <= THREADS, "x-pass: one thread per row segment");
+    static_assert(D % 2 == 0, "buffer parity must be static in the unrolled ring");
+    static_assert(LX % 4 == 0, "x-pass reads 16-byte aligned rows");
+};
+
+template <int R, int TY>
+struct M9Smem {
+    using S = M9Shape<R, TY>;
+    uint32_t raw[2][S::NLOAD * S::THREADS];
+    uint32_t px[2][S::LY * S::PXP];
+    uint32_t qx[2][S::LY * S::PXP];
+};
+
+template <int R, int TY, typename T, bool GATE>
+__device__ __forceinline__ void mean9_tile(M9Smem<R, TY>& sm, const T* __restrict__ in,
+                                           T* __restrict__ out, Geom g, int x0, int y0, int z0,
+                                           int z1, uint32_t gate, double inv9n)
+{
+    using S = M9Shape<R, TY>;
+    constexpr int H = S::H, LX = S::LX, D = S::D, TX = S::TX, PXP = S::PXP, YO = S::YO;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const size_t plane = (size_t)g.nx * g.ny;
+    const uint32_t pbytes = (uint32_t)(plane * sizeof(T));
+
+    // byte offsets (within a slice) of the raw elements this lane stages
+    uint32_t off[S::NLOAD];
+#pragma unroll
+    for (int i = 0; i < S::NLOAD; ++i) {
+        const int e = min(tid + i * S::THREADS, S::NRAW - 1);
+        const int row = e / LX, col = e - row * LX;
+        const int gy = clampi(y0 - H + row, 0, g.ny - 1);
+        const int gx = clampi(x0 - H + col, 0, g.nx - 1);
+        off[i] = (uint32_t)(gy * g.nx + gx) * (uint32_t)sizeof(T);
+    }
+    const bool last_ok = tid + (S::NLOAD - 1) * S::THREADS < S::NRAW;
+
+    auto stage = [&](int zi, int buf) {
+        const rsrc_t rs = make_rsrc(in + (size_t)clampi(zi, 0, g.nz - 1) * plane, pbytes);
+#pragma unroll
+        for (int i = 0; i < S::NLOAD; ++i)
+            if (i < S::NFULL || last_ok)
+                buffer_load_lds<T>(rs, &sm.raw[buf][i * S::THREADS + wave * 64], off[i]);
+    };
+
+    const int xrow = tid / S::NSEG, xseg = tid % S::NSEG;
+    const bool xactive = xrow < S::LY;
+    auto xpass = [&](int buf) {
+        if (!xactive) return;
+        uint32_t w[S::SW], c[S::SW];
+        const uint32_t* rp = sm.raw[buf] + xrow * LX + xseg * S::SEG;
+#pragma unroll
+        for (int i = 0; i < S::SW; i += 4) {
+            const uint4 t4 = *reinterpret_cast<const uint4*>(rp + i);
+            w[i] = t4.x;
+            w[i + 1] = t4.y;
+            w[i + 2] = t4.z;
+            w[i + 3] = t4.w;
+        }
+        c[0] = w[0];
+#pragma unroll
+        for (int i = 1; i < S::SW; ++i) c[i] = c[i - 1] + w[i];
+        uint32_t pp[S::SEG], qq[S::SEG];
+#pragma unroll
+        for (int m = 0; m < S::SEG; ++m) {
+            qq[m] = c[m + 4 * R] - (m ? c[m - 1] : 0u) + w[m + 2 * R];
+            pp[m] = c[m + 3 * R] - c[m + R - 1];
+        }
+        uint32_t* pd = sm.px[buf] + xrow * PXP + xseg * S::SEG;
+        uint32_t* qd = sm.qx[buf] + xrow * PXP + xseg * S::SEG;
+#pragma unroll
+        for (int m = 0; m < S::SEG; m += 4) {
+            *reinterpret_cast<uint4*>(pd + m) = make_uint4(pp[m], pp[m + 1], pp[m + 2], pp[m + 3]);
+            *reinterpret_cast<uint4*>(qd + m) = make_uint4(qq[m], qq[m + 1], qq[m + 2], qq[m + 3]);
+        }
+    };
+
+    // y-pass / ring ownership: column xq, rows yg*YO .. yg*YO+YO-1
+    const int xq = tid % TX, yg = tid / TX;
+    const int xo = x0 + xq, ybase = y0 + yg * YO;
+    const uint32_t voff = (uint32_t)((size_t)ybase * g.nx + xo) * (uint32_t)sizeof(T);
+    const uint32_t rowb = (uint32_t)g.nx * (uint32_t)sizeof(T);
+    bool ok[YO];
+#pragma unroll
+    for (int m = 0; m < YO; ++m) ok[m] = xo < g.nx && ybase + m < g.ny;
+
+    uint32_t pr[D][YO], qr[D][YO], bacc[YO], wacc[YO];
+#pragma unroll
+    for (int m = 0; m < YO; ++m) {
+        bacc[m] = wacc[m] = 0;
+#pragma unroll
+        for (int u = 0; u < D; ++u) pr[u][m] = qr[u][m] = 0;
+    }
+
+    const int ns = (z1 - z0) + 2 * H;  // input slices z0-2r .. z1-1+2r
+    stage(z0 - H, 0);
+    wait_vmem();
+    __syncthreads();
+    for (int kb = 0; kb <= ns; kb += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int k = kb + u;  // x-pass of slice k, y-pass of slice k-1
+            if (k > ns) break;
+            const int buf = u & 1;  // == k & 1 because D is even
+            // y-pass, ring and stores of slice k-1 first, so the stores are on
+            // their way before this iteration's wait
+            if (k >= 1) {
+                const int pb = buf ^ 1;
+                uint32_t cp[S::NPV], cq[S::NQV], qc[YO];
+                cp[0] = sm.px[pb][(yg * YO + R) * PXP + xq];
+#pragma unroll
+                for (int i = 1; i < S::NPV; ++i)
+                    cp[i] = cp[i - 1] + sm.px[pb][(yg * YO + R + i) * PXP + xq];
+                {
+                    uint32_t qv[S::NQV];
+#pragma unroll
+                    for (int i = 0; i < S::NQV; ++i) qv[i] = sm.qx[pb][(yg * YO + i) * PXP + xq];
+                    cq[0] = qv[0];
+#pragma unroll
+                    for (int i = 1; i < S::NQV; ++i) cq[i] = cq[i - 1] + qv[i];
+#pragma unroll
+                    for (int m = 0; m < YO; ++m) qc[m] = qv[m + 2 * R];
+                }
+                const int uj = (u + D - 1) % D;  // ring slot of slice j = k-1
+#pragma unroll
+                for (int m = 0; m < YO; ++m) {
+                    const uint32_t P = cp[m + 2 * R] - (m ? cp[m - 1] : 0u);
+                    const uint32_t Q = cq[m + 4 * R] - (m ? cq[m - 1] : 0u) + qc[m];
+                    bacc[m] += pr[(uj + D - R) % D][m] - pr[(uj + R + 1) % D][m];
+                    wacc[m] += Q - qr[(uj + 1) % D][m];
+                    pr[uj][m] = P;
+                    qr[uj][m] = Q;
+                }
+                const int j = k - 1;
+                if (j >= 2 * H) {
+                    const int z = z0 + j - 2 * H;
+                    const rsrc_t wr = make_rsrc(out + (size_t)z * plane, pbytes);
+#pragma unroll
+                    for (int m = 0; m < YO; ++m) {
+                        const uint32_t Ssum = bacc[m] + wacc[m] + qr[(uj + D - 2 * R) % D][m];
+                        uint32_t o = round_div_odd(Ssum, inv9n);
+                        if (GATE && o < gate) o = 0;
+                        if (ok[m]) buffer_store<T>(o, wr, voff, (uint32_t)m * rowb);
+                    }
+                }
+            }
+            if (k + 1 < ns) stage(z0 - H + k + 1, buf ^ 1);
+            if (k < ns) xpass(buf);
+            wait_vmem();
+            __syncthreads();
+        }
+    }
+}
+
+}  // namespace lnf

@@ -161,6 +161,17 @@ def _shape_params(dims, spec: PhantomSpec, rng: np.random.Generator):
     return shapes
 
 
+def _z_extent(sh):
+    """Conservative z-range of a shape (voxel-centre coordinates)."""
+    if sh[0] == "ellipsoid":
+        c, semi = sh[1], sh[2]
+        e = max(semi)
+    else:
+        c, ax, rad, half = sh[1], sh[2], sh[3], sh[4]
+        e = abs(ax[2]) * half + rad + 1.0
+    return c[2] - e - 1.0, c[2] + e + 1.0
+
+
 def phantom_device(dims, spec: PhantomSpec, seed: int, device, slab: int = 64):
     """The same recipe as `phantom`, rasterised and noised on a torch device.
 
@@ -186,6 +197,9 @@ def phantom_device(dims, spec: PhantomSpec, seed: int, device, slab: int = 64):
         clean = torch.full((z1 - z0, ny, nx), float(spec.background * spec.scale),
                            dtype=torch.float32, device=device)
         for sh in shapes:
+            zlo, zhi = _z_extent(sh)
+            if zhi < z0 or zlo > z1 - 1:
+                continue
             if sh[0] == "ellipsoid":
                 _, c, semi, rot, val = sh
                 a = rot @ np.diag(1.0 / np.asarray(semi) ** 2) @ rot.T
@@ -275,8 +289,11 @@ def batch_jobs(n: int = 64, seed: int = 4000, lo: int = 64, hi: int = 384):
     return jobs
 
 
-def batch_volume(job: BatchJob) -> np.ndarray:
+def batch_volume(job: BatchJob, device=None):
+    """Volume of one batch job (numpy, or a tensor generated on `device`)."""
     spec = SPEC_U8 if job.dtype == np.uint8 else SPEC_U8X16
+    if device is not None:
+        return phantom_device(job.dims, spec, job.seed, device)
     return phantom(job.dims, spec, job.seed)
 
 
