@@ -86,6 +86,79 @@ def batch_benchmark(rule_code, stream, steps=5):
             "batch_GBps": nbytes / (ms_b * 1e-3) / 1e9}
 
 
+def serve_benchmark(rule_code, seconds, rate=300.0, pool_n=8, side=512):
+    """Open-loop Poisson replay of the serving trace against the server, once
+    with continuous batching and once with one lnf_filter per request in FIFO
+    order (same trace).  30% of requests re-filter a resident volume at a new
+    radius; the others upload a new volume dense from a contiguous chunk of a
+    pinned pool of 512^3 uint16 phantoms (the phantom's value statistics, the
+    request's cube size).  Latency = completion - scheduled arrival."""
+    import torch
+    from paper_1807_03119_amd import _lib, phantom
+    from paper_1807_03119_amd.api import Filter, Server
+    pool = []
+    for i in range(pool_n):
+        v = phantom.ct_u12((side, side, side), seed=5100 + i, device="cuda")
+        hbuf = torch.empty(v.shape, dtype=torch.uint16, pin_memory=True)
+        hbuf.copy_(v)
+        pool.append(hbuf)
+        del v
+    torch.cuda.synchronize()
+    log(f"  serve: pool of {pool_n} pinned phantoms ready")
+    trace = phantom.serve_trace(rate=rate, duration=seconds)
+    offered = sum(r.side ** 3 for r in trace)
+    out = {"requests": len(trace), "seconds": seconds, "rate_per_s": rate,
+           "offered_Gvox_s": offered / seconds / 1e9, "pool_volumes": pool_n,
+           "cap_bytes": 200 << 30}
+    for name, mode in (("batched", _lib.LNF_SERVE_BATCHED), ("fifo", _lib.LNF_SERVE_FIFO)):
+        f = Filter(rule_code, 0)
+        srv = Server(f, cap_bytes=200 << 30, n_streams=4, max_batch=256, mode=mode)
+        residents, rejected, lag_max = [], 0, 0.0
+        t0 = _lib.lnf_server_now_ns() + 200_000_000
+        wall0 = time.perf_counter()
+        for k, req in enumerate(trace):
+            due = t0 + int(req.t_arrival * 1e9)
+            while True:
+                now = _lib.lnf_server_now_ns()
+                if now >= due:
+                    break
+                if due - now > 1_000_000:
+                    time.sleep((due - now - 500_000) * 1e-9)
+            lag_max = max(lag_max, (now - due) * 1e-6)
+            if k % 500 == 0:
+                log(f"  serve[{name}] request {k}/{len(trace)} trace t={req.t_arrival:.1f}s "
+                    f"wall {time.perf_counter() - wall0:.1f}s lag {(now - due) * 1e-6:.1f} ms")
+            if req.refilter and residents:
+                vid = residents[int(req.pick * len(residents))]
+                rc, _t = srv.submit(vid, req.radius, arrival_ns=due)
+                if rc == 0:
+                    continue
+                residents.remove(vid)
+            # a new volume arrives dense: a contiguous chunk of pinned phantom data
+            src = pool[req.pool_index % pool_n]
+            nvox = req.side ** 3
+            o = int(req.pick * (src.numel() - nvox)) // 256 * 256
+            rc, vid = srv.put(src.data_ptr() + 2 * o, dims=(req.side,) * 3, dtype=_lib.LNF_U16)
+            if rc != 0:
+                rejected += 1
+                continue
+            residents.append(vid)
+            rc, _t = srv.submit(vid, req.radius, arrival_ns=due)
+            if rc != 0:
+                rejected += 1
+        srv.sync()
+        st = srv.stats()
+        out[name] = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "max_ms": st["max_ms"],
+                     "mean_ms": st["mean_ms"], "completed": st["completed"],
+                     "failed": st["failed"], "rejected": rejected, "batches": st["batches"],
+                     "uploads": st["uploads"], "evictions": st["evictions"],
+                     "served_Gvox_s": st["gvox_per_s"], "peak_GB": st["peak_bytes"] / 1e9,
+                     "client_lag_max_ms": lag_max}
+        srv.close()
+        f.close()
+    return out
+
+
 def cpu_baseline(vol_np, radius, rule, got_np, budget_s=12.0):
     """Time the oracle on whole z-slices of the same volume; verify them too."""
     import numpy as np
@@ -125,6 +198,8 @@ def main():
     ap.add_argument("--rule", choices=["mean9", "minvar9"], default="mean9")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the served-mode trace (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -184,6 +259,9 @@ def main():
         log("timing the 64-volume mixed batch")
         extras["batch64"] = batch_benchmark(rule_code, stream)
         res["extras"] = extras
+        if args.serve_seconds > 0:
+            log(f"serving trace: {args.serve_seconds:.0f} s at 300 req/s, batched then FIFO")
+            res["served"] = serve_benchmark(rule_code, args.serve_seconds)
     if not args.no_cpu_baseline:
         f(vol, args.radius, out=out)
         torch.cuda.synchronize()

@@ -159,6 +159,99 @@ LNF_API int lnf_tune(lnf_handle h, const lnf_job* sample, int n);
 LNF_API int lnf_tune_save(lnf_handle h, const char* path);
 LNF_API int lnf_tune_load(lnf_handle h, const char* path);
 
+/* ---- serving ------------------------------------------------------------ */
+/*
+ * A request server with continuous batching.  Volumes are uploaded once and
+ * stay resident in library-owned device memory; filter requests against them
+ * (at any radius) are queued, admitted while the device footprint (resident
+ * volumes + request outputs + cached blocks) stays under the cap, grouped
+ * into micro-batches of everything admitted so far, and launched through the
+ * batch path on a pool of streams, so batches issued while others run overlap
+ * on the device.  Idle volumes are evicted least-recently-used first when the
+ * cap is reached.  A worker thread owned by the server does the scheduling and
+ * completion polling; every function below is thread-safe.
+ * Latency of a request = completion observed by the worker - its arrival time
+ * (the client's scheduled arrival, so queueing delay is never hidden).
+ */
+typedef struct lnf_server* lnf_server_handle;
+
+#define LNF_SERVE_BATCHED 0   /* continuous batching over n_streams streams */
+#define LNF_SERVE_FIFO 1      /* reference: one lnf_filter per request, in order, one stream */
+
+typedef struct {
+    uint32_t size;            /* sizeof(lnf_server_options) */
+    int32_t mode;             /* LNF_SERVE_BATCHED or LNF_SERVE_FIFO */
+    uint64_t cap_bytes;       /* device-memory cap of the server (> 0) */
+    int32_t n_streams;        /* streams micro-batches are spread over (1..16) */
+    int32_t max_batch;        /* most requests per micro-batch (1..LNF_BATCH_MAX) */
+    int32_t fail_batch;       /* test hook: the n-th batch (1-based) fails on the host
+                                 before launch and its requests end LNF_ECANCELED; 0 = off */
+    int32_t reserved;
+} lnf_server_options;
+
+typedef struct {
+    uint64_t submitted, completed, failed, cancelled, batches, evictions, uploads;
+    uint64_t voxels;          /* voxels filtered by completed requests */
+    uint64_t bytes_in_use;    /* current device footprint */
+    uint64_t peak_bytes;      /* largest footprint seen */
+    double p50_ms, p99_ms, max_ms, mean_ms;  /* latency of completed requests */
+    double busy_s;            /* first arrival to last completion */
+    double gvox_per_s;        /* voxels / busy_s */
+} lnf_server_stats_t;
+
+/* Steady clock (ns) the server measures latency with; use it for arrival times. */
+LNF_API int64_t lnf_server_now_ns(void);
+
+/* Create a server over context h (its rule and gate apply).  opt NULL: batched,
+ * 200 GB cap, 4 streams, max_batch 256.  Errors: LNF_EINVAL, LNF_EHIP, LNF_ENOMEM. */
+LNF_API int lnf_server_create(lnf_handle h, const lnf_server_options* opt, lnf_server_handle* srv);
+
+/* Finish all admitted work, fail still-pending requests with LNF_ECANCELED, free
+ * everything.  NULL is a no-op. */
+LNF_API int lnf_server_destroy(lnf_server_handle srv);
+
+/*
+ * Upload a host volume (asynchronously; pinned host memory gives a true DMA)
+ * into a new resident volume.  host_pitch, if not NULL, gives the source's row
+ * and slice pitch in elements ({row, slice}), so a crop of a larger host
+ * volume can be uploaded without packing it first.  The host buffer must stay
+ * valid until a request on the volume completes (or lnf_server_sync).
+ * Errors: LNF_EINVAL, LNF_EBUSY (cannot fit under the cap even after evicting
+ * every idle volume), LNF_ENOMEM, LNF_EHIP.
+ */
+LNF_API int lnf_server_put_volume(lnf_server_handle srv, const void* host, const int64_t dims[3],
+                                  int dtype, const int64_t* host_pitch, uint64_t* vol_id);
+
+/* Drop a resident volume once no request uses it.  Errors: LNF_ENOTFOUND. */
+LNF_API int lnf_server_release(lnf_server_handle srv, uint64_t vol_id);
+
+/*
+ * Queue a filter request: filter resident volume vol_id at `radius`.  If
+ * host_out is not NULL the result is copied there (dense layout, included in
+ * the latency).  arrival_ns: scheduled arrival on lnf_server_now_ns's clock;
+ * 0 = now.  Errors: LNF_EINVAL, LNF_ENOTFOUND.
+ */
+LNF_API int lnf_server_submit(lnf_server_handle srv, uint64_t vol_id, int radius, void* host_out,
+                              int64_t arrival_ns, uint64_t* ticket);
+
+/* Status of a request: *done = 1 once it completed or failed; returns LNF_OK,
+ * or the request's failure code once done, or LNF_ENOTFOUND. */
+LNF_API int lnf_server_poll(lnf_server_handle srv, uint64_t ticket, int* done);
+
+/* Block until the request completes (LNF_OK / its failure code) or timeout_ms
+ * passes (LNF_ETIMEDOUT; < 0 waits forever). */
+LNF_API int lnf_server_wait(lnf_server_handle srv, uint64_t ticket, int timeout_ms);
+
+/* Cancel a request that has not been admitted yet (LNF_OK), else LNF_EBUSY. */
+LNF_API int lnf_server_cancel(lnf_server_handle srv, uint64_t ticket);
+
+/* Block until every submitted request has finished. */
+LNF_API int lnf_server_sync(lnf_server_handle srv);
+
+/* Counters and latency percentiles; reset_latency != 0 clears the latency
+ * record and counters afterwards (resident volumes are kept). */
+LNF_API int lnf_server_stats(lnf_server_handle srv, lnf_server_stats_t* st, int reset);
+
 /* Human-readable text of a status code (static storage). */
 LNF_API const char* lnf_strerror(int code);
 

@@ -52,6 +52,22 @@ class lnf_job(ctypes.Structure):
 
 
 LNF_BATCH_MAX = 4096
+LNF_SERVE_BATCHED = 0
+LNF_SERVE_FIFO = 1
+
+
+class lnf_server_options(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("mode", ctypes.c_int32), ("cap_bytes", ctypes.c_uint64),
+                ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("fail_batch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class lnf_server_stats_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("submitted", "completed", "failed", "cancelled", "batches", "evictions", "uploads",
+                 "voxels", "bytes_in_use", "peak_bytes")] + \
+               [(n, ctypes.c_double) for n in
+                ("p50_ms", "p99_ms", "max_ms", "mean_ms", "busy_s", "gvox_per_s")]
 
 
 _lib = None
@@ -74,10 +90,26 @@ def _declare(lib):
         "lnf_tune_load": [_vp, ctypes.c_char_p],
         "lnf_version": [],
     }
+    _u64, _i64 = ctypes.c_uint64, ctypes.c_int64
+    sig.update({
+        "lnf_server_create": [_vp, ctypes.POINTER(lnf_server_options), ctypes.POINTER(_vp)],
+        "lnf_server_destroy": [_vp],
+        "lnf_server_put_volume": [_vp, _vp, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i64),
+                                  ctypes.POINTER(_u64)],
+        "lnf_server_release": [_vp, _u64],
+        "lnf_server_submit": [_vp, _u64, _i32, _vp, _i64, ctypes.POINTER(_u64)],
+        "lnf_server_poll": [_vp, _u64, ctypes.POINTER(_i32)],
+        "lnf_server_wait": [_vp, _u64, _i32],
+        "lnf_server_cancel": [_vp, _u64],
+        "lnf_server_sync": [_vp],
+        "lnf_server_stats": [_vp, ctypes.POINTER(lnf_server_stats_t), _i32],
+    })
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int
+    lib.lnf_server_now_ns.argtypes = []
+    lib.lnf_server_now_ns.restype = ctypes.c_int64
     lib.lnf_strerror.argtypes = [_i32]
     lib.lnf_strerror.restype = ctypes.c_char_p
 
@@ -230,3 +262,69 @@ def lnf_tune_save(h, path: str) -> int:
 
 def lnf_tune_load(h, path: str) -> int:
     return lib().lnf_tune_load(h, path.encode())
+
+
+# ---------------------------------------------------------------------------
+# server
+# ---------------------------------------------------------------------------
+
+def lnf_server_now_ns() -> int:
+    return lib().lnf_server_now_ns()
+
+
+def lnf_server_create(h, mode=LNF_SERVE_BATCHED, cap_bytes=200 << 30, n_streams=4, max_batch=256,
+                      fail_batch=0):
+    opt = lnf_server_options(ctypes.sizeof(lnf_server_options), mode, cap_bytes, n_streams,
+                             max_batch, fail_batch, 0)
+    srv = _vp()
+    _check(lib().lnf_server_create(h, ctypes.byref(opt), ctypes.byref(srv)), "lnf_server_create")
+    return srv
+
+
+def lnf_server_destroy(srv) -> int:
+    return lib().lnf_server_destroy(srv)
+
+
+def lnf_server_put_volume(srv, host_ptr: int, dims, dtype: int, pitch=None):
+    """Returns (rc, vol_id)."""
+    d = _dims_t(*[int(v) for v in dims])
+    p = (ctypes.c_int64 * 2)(*[int(v) for v in pitch]) if pitch is not None else None
+    vid = ctypes.c_uint64()
+    rc = lib().lnf_server_put_volume(srv, host_ptr, d, dtype, p, ctypes.byref(vid))
+    return rc, vid.value
+
+
+def lnf_server_release(srv, vol_id: int) -> int:
+    return lib().lnf_server_release(srv, vol_id)
+
+
+def lnf_server_submit(srv, vol_id: int, radius: int, host_out: int = 0, arrival_ns: int = 0):
+    """Returns (rc, ticket)."""
+    t = ctypes.c_uint64()
+    rc = lib().lnf_server_submit(srv, vol_id, radius, host_out or None, arrival_ns, ctypes.byref(t))
+    return rc, t.value
+
+
+def lnf_server_poll(srv, ticket: int):
+    """Returns (rc, done)."""
+    d = ctypes.c_int()
+    rc = lib().lnf_server_poll(srv, ticket, ctypes.byref(d))
+    return rc, bool(d.value)
+
+
+def lnf_server_wait(srv, ticket: int, timeout_ms: int = -1) -> int:
+    return lib().lnf_server_wait(srv, ticket, timeout_ms)
+
+
+def lnf_server_cancel(srv, ticket: int) -> int:
+    return lib().lnf_server_cancel(srv, ticket)
+
+
+def lnf_server_sync(srv) -> int:
+    return lib().lnf_server_sync(srv)
+
+
+def lnf_server_stats(srv, reset: bool = False) -> dict:
+    st = lnf_server_stats_t()
+    _check(lib().lnf_server_stats(srv, ctypes.byref(st), int(reset)), "lnf_server_stats")
+    return {name: getattr(st, name) for name, _ in lnf_server_stats_t._fields_}

@@ -97,3 +97,86 @@ def filter_volume(vol, radius: int, rule: int = LNF_MEAN9, gate: int = 0, out=No
     if f is None:
         f = _cache[key] = Filter(rule, gate, vol.device.index)
     return f(vol, radius, out=out, stream=stream)
+
+
+class Server:
+    """Request server over a Filter context (continuous batching).
+
+    Host buffers handed to `put` / `submit` are referenced until the request
+    using them completes; this wrapper keeps them alive until `sync`/`close`.
+    """
+
+    def __init__(self, filt: Filter, cap_bytes: int = 200 << 30, n_streams: int = 4,
+                 max_batch: int = 256, mode: int = _lib.LNF_SERVE_BATCHED, fail_batch: int = 0):
+        self.filt = filt
+        self._s = _lib.lnf_server_create(filt.handle, mode, cap_bytes, n_streams, max_batch,
+                                         fail_batch)
+        self._keep = []
+
+    def put(self, host, dims=None, dtype=None, pitch=None, keep=None):
+        """Upload a host volume (contiguous torch CPU tensor or numpy array, or a raw
+        pointer with explicit dims/dtype); returns (rc, vol_id)."""
+        if isinstance(host, int):
+            ptr = host
+        else:
+            import numpy as np
+            if isinstance(host, np.ndarray):
+                ptr = host.ctypes.data
+                dt = host.dtype
+                dtype = dtype or (_lib.LNF_U8 if dt == np.uint8 else _lib.LNF_U16)
+            else:
+                ptr = host.data_ptr()
+                dtype = dtype or _lib.dtype_code(host)
+            if dims is None:
+                nz, ny, nx = host.shape
+                dims = (nx, ny, nz)
+            self._keep.append(host)
+        if keep is not None:
+            self._keep.append(keep)
+        return _lib.lnf_server_put_volume(self._s, ptr, dims, dtype, pitch)
+
+    def submit(self, vol_id, radius, host_out=None, arrival_ns=0):
+        ptr = 0
+        if host_out is not None:
+            ptr = host_out if isinstance(host_out, int) else (
+                host_out.ctypes.data if hasattr(host_out, "ctypes") else host_out.data_ptr())
+            self._keep.append(host_out)
+        return _lib.lnf_server_submit(self._s, vol_id, radius, ptr, arrival_ns)
+
+    def wait(self, ticket, timeout_ms=-1):
+        return _lib.lnf_server_wait(self._s, ticket, timeout_ms)
+
+    def poll(self, ticket):
+        return _lib.lnf_server_poll(self._s, ticket)
+
+    def cancel(self, ticket):
+        return _lib.lnf_server_cancel(self._s, ticket)
+
+    def release(self, vol_id):
+        return _lib.lnf_server_release(self._s, vol_id)
+
+    def sync(self):
+        rc = _lib.lnf_server_sync(self._s)
+        self._keep.clear()
+        return rc
+
+    def stats(self, reset=False):
+        return _lib.lnf_server_stats(self._s, reset)
+
+    def close(self):
+        if self._s is not None:
+            _lib.lnf_server_destroy(self._s)
+            self._s = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
