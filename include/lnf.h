@@ -159,6 +159,35 @@ LNF_API int lnf_tune(lnf_handle h, const lnf_job* sample, int n);
 LNF_API int lnf_tune_save(lnf_handle h, const char* path);
 LNF_API int lnf_tune_load(lnf_handle h, const char* path);
 
+/* ---- Otsu threshold and the gated pipeline ---------------------------- */
+/*
+ * Grey-level histogram: hist[v] = number of voxels equal to v.  `hist` is
+ * device memory of 256 (LNF_U8) or 65536 (LNF_U16) uint64 counters, cleared
+ * and filled by the call (asynchronous on `stream`).
+ * Errors: LNF_EINVAL (nulls, dtype, dims, hist overlapping vol), LNF_EDEVICE, LNF_EHIP.
+ */
+LNF_API int lnf_histogram(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                          uint64_t* hist, hipStream_t stream);
+
+/*
+ * Otsu's data threshold of a host histogram (paper, Section "Our Method",
+ * eq. 1): the T minimising the within-class variance, computed exactly as the
+ * T maximising (N*s0 - n0*S)^2 / (n0*n1) with class 0 = levels below T.
+ * Lowest T among equal optima; if fewer than two levels are present, T is
+ * the present level (0 for an empty histogram).  Host only, no GPU.
+ * Errors: LNF_EINVAL (nulls, levels not in 1..65536).
+ */
+LNF_API int lnf_otsu_threshold(const uint64_t* hist, int levels, uint32_t* T);
+
+/*
+ * The paper's automatic pipeline: T = Otsu threshold of `vol`, then the
+ * context's rule gated at T (the context's own gate_T is not used).  Reads
+ * the histogram back, so `stream` is synchronised once; *T (if not NULL)
+ * receives the threshold.  Errors: as lnf_filter, LNF_ENOMEM.
+ */
+LNF_API int lnf_filter_otsu(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                            int radius, void* out, hipStream_t stream, uint32_t* T);
+
 /* ---- serving ------------------------------------------------------------ */
 /*
  * A request server with continuous batching.  Volumes are uploaded once and

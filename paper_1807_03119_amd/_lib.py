@@ -89,6 +89,10 @@ def _declare(lib):
         "lnf_tune_save": [_vp, ctypes.c_char_p],
         "lnf_tune_load": [_vp, ctypes.c_char_p],
         "lnf_version": [],
+        "lnf_histogram": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _vp, _vp],
+        "lnf_otsu_threshold": [_vp, _i32, ctypes.POINTER(ctypes.c_uint32)],
+        "lnf_filter_otsu": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, _vp, _vp,
+                            ctypes.POINTER(ctypes.c_uint32)],
     }
     _u64, _i64 = ctypes.c_uint64, ctypes.c_int64
     sig.update({
@@ -328,3 +332,34 @@ def lnf_server_stats(srv, reset: bool = False) -> dict:
     st = lnf_server_stats_t()
     _check(lib().lnf_server_stats(srv, ctypes.byref(st), int(reset)), "lnf_server_stats")
     return {name: getattr(st, name) for name, _ in lnf_server_stats_t._fields_}
+
+
+# ---------------------------------------------------------------------------
+# Otsu threshold and gated pipeline
+# ---------------------------------------------------------------------------
+
+def lnf_histogram(h, vol, dims, dtype: int, hist, stream=None) -> int:
+    vp = vol if isinstance(vol, int) else vol.data_ptr()
+    hp = hist if isinstance(hist, int) else hist.data_ptr()
+    return lib().lnf_histogram(h, vp, _dims_t(*[int(v) for v in dims]), dtype, hp,
+                               stream_ptr(stream))
+
+
+def lnf_otsu_threshold(hist) -> int:
+    """Otsu threshold of a host histogram (numpy-compatible sequence of counts)."""
+    import numpy as np
+    arr = np.ascontiguousarray(np.asarray(hist, dtype=np.uint64))
+    t = ctypes.c_uint32()
+    _check(lib().lnf_otsu_threshold(arr.ctypes.data, int(arr.size), ctypes.byref(t)),
+           "lnf_otsu_threshold")
+    return t.value
+
+
+def lnf_filter_otsu(h, vol, dims, dtype: int, radius: int, out, stream=None):
+    """Returns (rc, T)."""
+    vp = vol if isinstance(vol, int) else vol.data_ptr()
+    op = out if isinstance(out, int) else out.data_ptr()
+    t = ctypes.c_uint32()
+    rc = lib().lnf_filter_otsu(h, vp, _dims_t(*[int(v) for v in dims]), dtype, radius, op,
+                               stream_ptr(stream), ctypes.byref(t))
+    return rc, t.value

@@ -45,6 +45,29 @@ class Filter:
             raise LnfError(rc, "lnf_filter")
         return out
 
+    def filter_otsu(self, vol, radius: int, out=None, stream=None):
+        """The paper's automatic pipeline: Otsu threshold of `vol`, then the filter
+        gated at it.  Returns (out, T)."""
+        import torch
+        _require_cuda(vol, "vol")
+        if out is None:
+            out = torch.empty_like(vol)
+        rc, t = _lib.lnf_filter_otsu(self._h, vol, _lib.dims_of(vol), _lib.dtype_code(vol),
+                                     int(radius), out, stream)
+        if rc != _lib.LNF_OK:
+            raise LnfError(rc, "lnf_filter_otsu")
+        return out, t
+
+    def histogram(self, vol, stream=None):
+        import torch
+        _require_cuda(vol, "vol")
+        levels = 256 if vol.dtype == torch.uint8 else 65536
+        hist = torch.empty(levels, dtype=torch.int64, device=vol.device)
+        rc = _lib.lnf_histogram(self._h, vol, _lib.dims_of(vol), _lib.dtype_code(vol), hist, stream)
+        if rc != _lib.LNF_OK:
+            raise LnfError(rc, "lnf_histogram")
+        return hist
+
     def batch(self, items, stream=None):
         """Filter [(vol, radius), ...] (or [(vol, out, radius), ...]) in one graph
         launch; returns the list of outputs."""

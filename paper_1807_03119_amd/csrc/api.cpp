@@ -117,6 +117,7 @@ int ctx_init_device_state(lnf_ctx* c)
 void ctx_free_device_state(lnf_ctx* c)
 {
     batch_state_free(c);
+    otsu_scratch_free(c);
     c->dev_state = nullptr;
 }
 

@@ -28,6 +28,9 @@ struct lnf_ctx {
     std::unordered_map<lnf::TuneKey, lnf::TileCfg> tuned;
     void* dev_state = nullptr;  // library-internal device memory (see ctx_init_device_state)
     lnf::BatchState* batch = nullptr;  // created on the first lnf_filter_batch call
+    std::mutex otsu_mu;                 // guards the Otsu scratch below
+    uint64_t* otsu_dev = nullptr;       // 65536 histogram counters (lnf_filter_otsu)
+    uint64_t* otsu_host = nullptr;      // pinned copy read by the host
 };
 
 namespace lnf {
@@ -54,6 +57,7 @@ hipError_t launch_rule(int rule, const void* in, void* out, int dtype, int r, Ge
 // Batch path (batch.hip).
 int validate_jobs(const lnf_ctx* h, const lnf_job* jobs, int n, std::vector<Geom>* geoms);
 void batch_state_free(lnf_ctx* h);
+void otsu_scratch_free(lnf_ctx* h);
 
 // Allocate / release the context's internal device memory.
 int ctx_init_device_state(lnf_ctx* c);

@@ -185,20 +185,20 @@ __global__ __launch_bounds__(kThreads) void mean9_ring_64x16(const T* __restrict
 }
 
 // Single-volume wrapper around the streaming tile body of mean9_tile.h.
-template <int R, int TY, typename T, bool GATE>
-__global__ __launch_bounds__((M9Shape<R, TY>::THREADS)) void mean9_stream(
+template <int R, int TY, typename T, bool GATE, int TXW = 64>
+__global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS)) void mean9_stream(
     const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
     int total, uint32_t gate, double inv9n)
 {
-    __shared__ __align__(16) M9Smem<R, TY> sm;
+    __shared__ __align__(16) M9Smem<R, TY, TXW> sm;
     const int tile = xcd_tile(blockIdx.x, total);
     const int bx = tile % tiles_x;
     const int rest = tile / tiles_x;
     const int by = rest % tiles_y;
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
-    mean9_tile<R, TY, T, GATE>(sm, in, out, g, bx * 64, by * TY, z0, min(z0 + zs, g.nz), gate,
-                               inv9n);
+    mean9_tile<R, TY, T, GATE, TXW>(sm, in, out, g, bx * TXW, by * TY, z0, min(z0 + zs, g.nz),
+                                    gate, inv9n);
 }
 
 struct Variant {
@@ -206,8 +206,9 @@ struct Variant {
     int target_groups;  // default z-strip depth aims at this many workgroups
 };
 // 0: first design (two barriers per slice, register staging)
-// 1, 2: LDS-DMA staging, double buffering, one barrier per slice
-constexpr Variant kVariants[] = {{64, 16, 256, 1024}, {64, 16, 256, 1024}, {64, 32, 512, 512}};
+// 1-4: LDS-DMA staging, double buffering, one barrier per slice; 64 or 32 wide
+constexpr Variant kVariants[] = {{64, 16, 256, 1024}, {64, 16, 256, 1024}, {64, 32, 512, 512},
+                                 {32, 16, 128, 2048}, {32, 32, 256, 1024}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kDefaultVariant = 1;
 
@@ -233,8 +234,16 @@ hipError_t launch_variant(int variant, const void* in, void* out, Geom g, uint32
         hipLaunchKernelGGL((mean9_stream<R, 16, T, GATE>), dim3(total), dim3(v.threads), 0, s,
                            pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
         break;
-    default:
+    case 2:
         hipLaunchKernelGGL((mean9_stream<R, 32, T, GATE>), dim3(total), dim3(v.threads), 0, s,
+                           pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
+        break;
+    case 3:
+        hipLaunchKernelGGL((mean9_stream<R, 16, T, GATE, 32>), dim3(total), dim3(v.threads), 0, s,
+                           pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
+        break;
+    default:
+        hipLaunchKernelGGL((mean9_stream<R, 32, T, GATE, 32>), dim3(total), dim3(v.threads), 0, s,
                            pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
         break;
     }

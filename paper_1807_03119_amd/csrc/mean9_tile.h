@@ -1,4 +1,4 @@
-// Streaming MEAN9 tile body: one workgroup filters a 64 x TY column of output
+// Streaming MEAN9 tile body: one workgroup filters a TX x TY column of output
 // voxels over the z-range [z0, z1).  Shared by the single-volume kernel and the
 // persistent batch kernel.
 //
@@ -9,7 +9,7 @@
 //
 // Pipeline per input slice k (one barrier per slice; stages listed in the
 // order they are issued within one iteration):
-//   - LDS DMA: the raw (64+4r) x (TY+4r) tile of slice k+1 is loaded straight
+//   - LDS DMA: the raw (TX+4r) x (TY+4r) tile of slice k+1 is loaded straight
 //     from HBM into LDS (one element per lane, zero-extended to 32 bits), its
 //     coordinates clamped into the volume per lane;
 //   - x-pass of slice k: each thread takes an 8-wide row segment, forms prefix
@@ -29,9 +29,9 @@
 
 namespace lnf {
 
-template <int R, int TY>
+template <int R, int TY, int TXW = 64>
 struct M9Shape {
-    static constexpr int TX = 64;
+    static constexpr int TX = TXW;
     static constexpr int YO = 4;                    // output rows per thread
     static constexpr int THREADS = TX * TY / YO;    // one thread per column x YO rows
     static constexpr int H = 2 * R;                 // halo: cluster radius + offset
@@ -48,20 +48,20 @@ struct M9Shape {
     static_assert(LX % 4 == 0, "x-pass reads 16-byte aligned rows");
 };
 
-template <int R, int TY>
+template <int R, int TY, int TXW = 64>
 struct M9Smem {
-    using S = M9Shape<R, TY>;
+    using S = M9Shape<R, TY, TXW>;
     uint32_t raw[2][S::NLOAD * S::THREADS];
     uint32_t px[2][S::LY * S::PXP];
     uint32_t qx[2][S::LY * S::PXP];
 };
 
-template <int R, int TY, typename T, bool GATE>
-__device__ __forceinline__ void mean9_tile(M9Smem<R, TY>& sm, const T* __restrict__ in,
+template <int R, int TY, typename T, bool GATE, int TXW = 64>
+__device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __restrict__ in,
                                            T* __restrict__ out, Geom g, int x0, int y0, int z0,
                                            int z1, uint32_t gate, double inv9n)
 {
-    using S = M9Shape<R, TY>;
+    using S = M9Shape<R, TY, TXW>;
     constexpr int H = S::H, LX = S::LX, D = S::D, TX = S::TX, PXP = S::PXP, YO = S::YO;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;

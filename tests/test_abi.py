@@ -72,3 +72,22 @@ def test_create_without_gpu_reports_device_error():
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
     assert _lib.lib().lnf_create(ctypes.byref(h), None) == _lib.LNF_EDEVICE
+
+
+def test_host_otsu_matches_oracle():
+    """The library's exact host-side Otsu (no GPU needed) against the oracle."""
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(4)
+    cases = [np.zeros(256, np.uint64), np.bincount([7] * 9, minlength=256)]
+    for _ in range(30):
+        levels = int(rng.choice([2, 3, 17, 256, 4096]))
+        h = rng.integers(0, 1000, levels).astype(np.uint64)
+        h[rng.integers(0, levels, levels // 3)] = 0
+        cases.append(h)
+    big = np.zeros(65536, np.uint64)
+    big[[100, 4000, 65535]] = [2 ** 40, 3 * 2 ** 39, 12345]  # huge counts: wide arithmetic
+    cases.append(big)
+    for h in cases:
+        assert _lib.lnf_otsu_threshold(h) == oracle.otsu_threshold(h)
