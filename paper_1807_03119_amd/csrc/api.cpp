@@ -92,9 +92,10 @@ TileCfg ctx_tile(const lnf_ctx* h, int rule, int dtype, int radius, Geom g)
 }
 
 hipError_t launch_rule(int rule, const void* in, void* out, int dtype, int r, Geom g,
-                       uint32_t gate, TileCfg cfg, hipStream_t s)
+                       uint32_t gate, TileCfg cfg, hipStream_t s, uint32_t flags)
 {
-    if (rule == LNF_MEAN9) return launch_mean9(in, out, dtype, r, g, gate, cfg, s);
+    if (rule == LNF_MEAN9)
+        return launch_mean9(in, out, dtype, r, g, gate, cfg, s, mean9_narrow(dtype, r, flags));
     return launch_minvar9(in, out, dtype, r, g, gate, cfg, s);
 }
 
@@ -155,7 +156,7 @@ int lnf_create(lnf_handle* h, const lnf_options* opt)
         o = *opt;
     }
     if (o.rule != LNF_MEAN9 && o.rule != LNF_MINVAR9) return LNF_EINVAL;
-    if (o.flags != 0) return LNF_EINVAL;
+    if (o.flags & ~LNF_FLAG_DATA_12BIT) return LNF_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         (void)hipGetLastError();
@@ -169,6 +170,7 @@ int lnf_create(lnf_handle* h, const lnf_options* opt)
     c->device = dev;
     c->rule = o.rule;
     c->gate = o.gate_T;
+    c->flags = o.flags;
     const int rc = ctx_init_device_state(c);
     if (rc != LNF_OK) {
         delete c;
@@ -217,7 +219,8 @@ int lnf_filter_tiled(lnf_handle h, const void* vol, const int64_t dims[3], int d
     if (!dg.ok()) return LNF_EHIP;
     if ((rc = check_device_range(vol, bytes, h->device))) return rc;
     if ((rc = check_device_range(out, bytes, h->device))) return rc;
-    if (launch_rule(h->rule, vol, out, dtype, radius, g, h->gate, cfg, stream) != hipSuccess)
+    if (launch_rule(h->rule, vol, out, dtype, radius, g, h->gate, cfg, stream, h->flags) !=
+        hipSuccess)
         return LNF_EHIP;
     return LNF_OK;
 }

@@ -28,8 +28,14 @@ int mean9_variants();
 int mean9_default_variant();
 // Tile footprint of a variant: output tile width/height in x/y.
 void mean9_tile_shape(int variant, int* tx, int* ty);
+// narrow: x-pass sums fit 16 bits (uint8 data, or 12-bit uint16 data with r <= 3)
 hipError_t launch_mean9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
-                        TileCfg cfg, hipStream_t s);
+                        TileCfg cfg, hipStream_t s, bool narrow);
+// Whether the narrow MEAN9 path is valid for (dtype, r) under the context flags.
+inline bool mean9_narrow(int dtype, int r, uint32_t flags)
+{
+    return dtype == LNF_U8 || ((flags & LNF_FLAG_DATA_12BIT) && r <= 3);
+}
 
 // ---- MINVAR9 (least-variance cluster) -------------------------------------
 int minvar9_variants();

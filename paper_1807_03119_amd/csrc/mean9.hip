@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void mean9_ring_64x16(const T* __restrict
 }
 
 // Single-volume wrapper around the streaming tile body of mean9_tile.h.
-template <int R, int TY, typename T, bool GATE, int TXW = 64>
+template <int R, int TY, typename T, bool GATE, int TXW = 64, bool NARROW = false>
 __global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS)) void mean9_stream(
     const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
     int total, uint32_t gate, double inv9n)
@@ -197,8 +197,8 @@ __global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS)) void mean9_stream(
     const int by = rest % tiles_y;
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
-    mean9_tile<R, TY, T, GATE, TXW>(sm, in, out, g, bx * TXW, by * TY, z0, min(z0 + zs, g.nz),
-                                    gate, inv9n);
+    mean9_tile<R, TY, T, GATE, TXW, NARROW>(sm, in, out, g, bx * TXW, by * TY, z0,
+                                            min(z0 + zs, g.nz), gate, inv9n);
 }
 
 struct Variant {
@@ -212,7 +212,7 @@ constexpr Variant kVariants[] = {{64, 16, 256, 1024}, {64, 16, 256, 1024}, {64, 
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kDefaultVariant = 1;
 
-template <int R, typename T, bool GATE>
+template <int R, typename T, bool GATE, bool NARROW>
 hipError_t launch_variant(int variant, const void* in, void* out, Geom g, uint32_t gate, int zs,
                           hipStream_t s)
 {
@@ -231,43 +231,49 @@ hipError_t launch_variant(int variant, const void* in, void* out, Geom g, uint32
                            pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
         break;
     case 1:
-        hipLaunchKernelGGL((mean9_stream<R, 16, T, GATE>), dim3(total), dim3(v.threads), 0, s,
-                           pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
+        hipLaunchKernelGGL((mean9_stream<R, 16, T, GATE, 64, NARROW>), dim3(total),
+                           dim3(v.threads), 0, s, pin, pout, g, zs, tiles_x, tiles_y, total, gate,
+                           inv9n);
         break;
     case 2:
-        hipLaunchKernelGGL((mean9_stream<R, 32, T, GATE>), dim3(total), dim3(v.threads), 0, s,
-                           pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
+        hipLaunchKernelGGL((mean9_stream<R, 32, T, GATE, 64, NARROW>), dim3(total),
+                           dim3(v.threads), 0, s, pin, pout, g, zs, tiles_x, tiles_y, total, gate,
+                           inv9n);
         break;
     case 3:
-        hipLaunchKernelGGL((mean9_stream<R, 16, T, GATE, 32>), dim3(total), dim3(v.threads), 0, s,
-                           pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
+        hipLaunchKernelGGL((mean9_stream<R, 16, T, GATE, 32, NARROW>), dim3(total),
+                           dim3(v.threads), 0, s, pin, pout, g, zs, tiles_x, tiles_y, total, gate,
+                           inv9n);
         break;
     default:
-        hipLaunchKernelGGL((mean9_stream<R, 32, T, GATE, 32>), dim3(total), dim3(v.threads), 0, s,
-                           pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
+        hipLaunchKernelGGL((mean9_stream<R, 32, T, GATE, 32, NARROW>), dim3(total),
+                           dim3(v.threads), 0, s, pin, pout, g, zs, tiles_x, tiles_y, total, gate,
+                           inv9n);
         break;
     }
     return hipGetLastError();
 }
 
-template <int R, typename T>
+template <int R, typename T, bool NARROW>
 hipError_t launch_r(int variant, const void* in, void* out, Geom g, uint32_t gate, int zs,
                     hipStream_t s)
 {
-    if (gate) return launch_variant<R, T, true>(variant, in, out, g, gate, zs, s);
-    return launch_variant<R, T, false>(variant, in, out, g, gate, zs, s);
+    if (gate) return launch_variant<R, T, true, NARROW>(variant, in, out, g, gate, zs, s);
+    return launch_variant<R, T, false, NARROW>(variant, in, out, g, gate, zs, s);
 }
 
-template <typename T>
+template <typename T, bool NARROW>
 hipError_t dispatch_r(const void* in, void* out, int r, Geom g, uint32_t gate, TileCfg cfg,
                       hipStream_t s)
 {
     const int v = (cfg.variant >= 0 && cfg.variant < kNumVariants) ? cfg.variant : kDefaultVariant;
     switch (r) {
-    case 1: return launch_r<1, T>(v, in, out, g, gate, cfg.zs, s);
-    case 2: return launch_r<2, T>(v, in, out, g, gate, cfg.zs, s);
-    case 3: return launch_r<3, T>(v, in, out, g, gate, cfg.zs, s);
-    case 4: return launch_r<4, T>(v, in, out, g, gate, cfg.zs, s);
+    case 1: return launch_r<1, T, NARROW>(v, in, out, g, gate, cfg.zs, s);
+    case 2: return launch_r<2, T, NARROW>(v, in, out, g, gate, cfg.zs, s);
+    case 3: return launch_r<3, T, NARROW>(v, in, out, g, gate, cfg.zs, s);
+    case 4:
+        if constexpr (NARROW && sizeof(T) == 2) return hipErrorInvalidValue;  // 12-bit: r <= 3
+        else return launch_r<4, T, NARROW>(v, in, out, g, gate, cfg.zs, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -285,10 +291,12 @@ void mean9_tile_shape(int variant, int* tx, int* ty)
 }
 
 hipError_t launch_mean9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
-                        TileCfg cfg, hipStream_t s)
+                        TileCfg cfg, hipStream_t s, bool narrow)
 {
-    if (dtype == LNF_U8) return dispatch_r<uint8_t>(in, out, r, g, gate, cfg, s);
-    return dispatch_r<uint16_t>(in, out, r, g, gate, cfg, s);
+    // uint8 data always fits the narrow path (x-pass sums <= 18 * 255)
+    if (dtype == LNF_U8) return dispatch_r<uint8_t, true>(in, out, r, g, gate, cfg, s);
+    if (narrow && r <= 3) return dispatch_r<uint16_t, true>(in, out, r, g, gate, cfg, s);
+    return dispatch_r<uint16_t, false>(in, out, r, g, gate, cfg, s);
 }
 
 }  // namespace lnf

@@ -29,6 +29,15 @@
 
 namespace lnf {
 
+using u16x2 = unsigned short __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 pack16(uint32_t lo, uint32_t hi)
+{
+    return __builtin_bit_cast(u16x2, (lo & 0xffffu) | (hi << 16));
+}
+
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
 template <int R, int TY, int TXW = 64>
 struct M9Shape {
     static constexpr int TX = TXW;
@@ -56,7 +65,11 @@ struct M9Smem {
     uint32_t qx[2][S::LY * S::PXP];
 };
 
-template <int R, int TY, typename T, bool GATE, int TXW = 64>
+// NARROW: every x-pass sum fits 16 bits (values <= 65535 / (4r+2)); the x-pass
+// then runs on row pairs packed in 16-bit halves and stores px / qx as row
+// pairs, halving their LDS traffic.  Packed prefix sums wrap modulo 2^16, which
+// leaves every window difference exact because each window sum is < 2^16.
+template <int R, int TY, typename T, bool GATE, int TXW = 64, bool NARROW = false>
 __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __restrict__ in,
                                            T* __restrict__ out, Geom g, int x0, int y0, int z0,
                                            int z1, uint32_t gate, double inv9n)
@@ -88,10 +101,46 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
                 buffer_load_lds<T>(rs, &sm.raw[buf][i * S::THREADS + wave * 64], off[i]);
     };
 
+    const int xq = tid % TX;
     const int xrow = tid / S::NSEG, xseg = tid % S::NSEG;
-    const bool xactive = xrow < S::LY;
+    const bool xactive = xrow < (NARROW ? S::LY / 2 : S::LY);
     auto xpass = [&](int buf) {
         if (!xactive) return;
+        if constexpr (NARROW) {
+            // rows 2*xrow and 2*xrow+1, packed as (low, high) 16-bit halves
+            u16x2 wp[S::SW], c[S::SW];
+            const uint32_t* r0 = sm.raw[buf] + (2 * xrow) * LX + xseg * S::SEG;
+            const uint32_t* r1 = r0 + LX;
+#pragma unroll
+            for (int i = 0; i < S::SW; i += 4) {
+                const uint4 a = *reinterpret_cast<const uint4*>(r0 + i);
+                const uint4 b = *reinterpret_cast<const uint4*>(r1 + i);
+                wp[i] = pack16(a.x, b.x);
+                wp[i + 1] = pack16(a.y, b.y);
+                wp[i + 2] = pack16(a.z, b.z);
+                wp[i + 3] = pack16(a.w, b.w);
+            }
+            c[0] = wp[0];
+#pragma unroll
+            for (int i = 1; i < S::SW; ++i) c[i] = c[i - 1] + wp[i];
+            uint32_t pp[S::SEG], qq[S::SEG];
+#pragma unroll
+            for (int m = 0; m < S::SEG; ++m) {
+                const u16x2 zero = {0, 0};
+                qq[m] = as_u32(c[m + 4 * R] - (m ? c[m - 1] : zero) + wp[m + 2 * R]);
+                pp[m] = as_u32(c[m + 3 * R] - c[m + R - 1]);
+            }
+            uint32_t* pd = sm.px[buf] + xrow * PXP + xseg * S::SEG;
+            uint32_t* qd = sm.qx[buf] + xrow * PXP + xseg * S::SEG;
+#pragma unroll
+            for (int m = 0; m < S::SEG; m += 4) {
+                *reinterpret_cast<uint4*>(pd + m) =
+                    make_uint4(pp[m], pp[m + 1], pp[m + 2], pp[m + 3]);
+                *reinterpret_cast<uint4*>(qd + m) =
+                    make_uint4(qq[m], qq[m + 1], qq[m + 2], qq[m + 3]);
+            }
+            return;
+        }
         uint32_t w[S::SW], c[S::SW];
         const uint32_t* rp = sm.raw[buf] + xrow * LX + xseg * S::SEG;
 #pragma unroll
@@ -120,8 +169,19 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
         }
     };
 
+    // Value of px (Q = false) or qx (Q = true) at x-pass row `row`, column xq.
+    auto xval = [&](int pb, bool q, int row) -> uint32_t {
+        const uint32_t* a = q ? sm.qx[pb] : sm.px[pb];
+        if constexpr (NARROW) {
+            const uint32_t w = a[(row >> 1) * PXP + xq];
+            return (row & 1) ? (w >> 16) : (w & 0xffffu);
+        } else {
+            return a[row * PXP + xq];
+        }
+    };
+
     // y-pass / ring ownership: column xq, rows yg*YO .. yg*YO+YO-1
-    const int xq = tid % TX, yg = tid / TX;
+    const int yg = tid / TX;
     const int xo = x0 + xq, ybase = y0 + yg * YO;
     const uint32_t voff = (uint32_t)((size_t)ybase * g.nx + xo) * (uint32_t)sizeof(T);
     const uint32_t rowb = (uint32_t)g.nx * (uint32_t)sizeof(T);
@@ -152,14 +212,13 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
             if (k >= 1) {
                 const int pb = buf ^ 1;
                 uint32_t cp[S::NPV], cq[S::NQV], qc[YO];
-                cp[0] = sm.px[pb][(yg * YO + R) * PXP + xq];
+                cp[0] = xval(pb, false, yg * YO + R);
 #pragma unroll
-                for (int i = 1; i < S::NPV; ++i)
-                    cp[i] = cp[i - 1] + sm.px[pb][(yg * YO + R + i) * PXP + xq];
+                for (int i = 1; i < S::NPV; ++i) cp[i] = cp[i - 1] + xval(pb, false, yg * YO + R + i);
                 {
                     uint32_t qv[S::NQV];
 #pragma unroll
-                    for (int i = 0; i < S::NQV; ++i) qv[i] = sm.qx[pb][(yg * YO + i) * PXP + xq];
+                    for (int i = 0; i < S::NQV; ++i) qv[i] = xval(pb, true, yg * YO + i);
                     cq[0] = qv[0];
 #pragma unroll
                     for (int i = 1; i < S::NQV; ++i) cq[i] = cq[i - 1] + qv[i];

@@ -62,7 +62,7 @@ def test_create_bad_options():
     assert lib.lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
     opt = _lib.lnf_options(4, 0, 0, -1, 0)
     assert lib.lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
-    opt = _lib.lnf_options(ctypes.sizeof(_lib.lnf_options), 0, 0, -1, 1)
+    opt = _lib.lnf_options(ctypes.sizeof(_lib.lnf_options), 0, 0, -1, 2)  # unknown flag bit
     assert lib.lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
 
 

@@ -130,3 +130,13 @@ def test_tune_keeps_results_and_cache_roundtrip(rule):
             open(bad, "w").write("12 not numbers\n")
             assert _lib.lnf_tune_load(f.handle, bad) == _lib.LNF_EINVAL
             assert _lib.lnf_tune_load(f.handle, os.path.join(d, "missing")) == _lib.LNF_EINVAL
+
+
+def test_batch_declared_12bit():
+    from paper_1807_03119_amd.api import Filter
+    jobs = [(ph.ct_u12((50, 40, 30), seed=60 + r), r) for r in (1, 2, 3, 4)]
+    jobs += [(ph.small_u8(70 + r, dims=(33, 20, 17)), r) for r in (1, 4)]
+    with Filter(_lib.LNF_MEAN9, 0, flags=_lib.LNF_FLAG_DATA_12BIT) as f:
+        outs = f.batch([(torch.from_numpy(v).cuda(), r) for v, r in jobs])
+        for (v, r), o in zip(jobs, outs):
+            np.testing.assert_array_equal(o.cpu().numpy(), oracle.filter_volume(v, r))
