@@ -194,6 +194,19 @@ LNF_API int lnf_otsu_threshold(const uint64_t* hist, int levels, uint32_t* T);
 LNF_API int lnf_filter_otsu(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
                             int radius, void* out, hipStream_t stream, uint32_t* T);
 
+/* ---- surface-point mode ------------------------------------------------ */
+/*
+ * The filter evaluated only at listed voxels, as the paper applies it at the
+ * first surface intersection point of each ray.  xyz: device int32 [n][3]
+ * (x, y, z); out: device uint32 [n] receives the filtered value (rule and gate
+ * of the context), or 0xFFFFFFFF for a point outside the volume.  Same value
+ * as lnf_filter at that voxel.  Asynchronous on `stream`.
+ * Errors: LNF_EINVAL, LNF_EDEVICE, LNF_EHIP.
+ */
+LNF_API int lnf_filter_points(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                              int radius, const int32_t* xyz, int64_t n, uint32_t* out,
+                              hipStream_t stream);
+
 /* ---- serving ------------------------------------------------------------ */
 /*
  * A request server with continuous batching.  Volumes are uploaded once and

@@ -91,6 +91,8 @@ def _declare(lib):
         "lnf_tune_load": [_vp, ctypes.c_char_p],
         "lnf_version": [],
         "lnf_histogram": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _vp, _vp],
+        "lnf_filter_points": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, _vp,
+                              ctypes.c_int64, _vp, _vp],
         "lnf_otsu_threshold": [_vp, _i32, ctypes.POINTER(ctypes.c_uint32)],
         "lnf_filter_otsu": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, _vp, _vp,
                             ctypes.POINTER(ctypes.c_uint32)],
@@ -364,3 +366,11 @@ def lnf_filter_otsu(h, vol, dims, dtype: int, radius: int, out, stream=None):
     rc = lib().lnf_filter_otsu(h, vp, _dims_t(*[int(v) for v in dims]), dtype, radius, op,
                                stream_ptr(stream), ctypes.byref(t))
     return rc, t.value
+
+
+def lnf_filter_points(h, vol, dims, dtype: int, radius: int, xyz, n: int, out, stream=None) -> int:
+    vp = vol if isinstance(vol, int) else vol.data_ptr()
+    xp = xyz if isinstance(xyz, int) else xyz.data_ptr()
+    op = out if isinstance(out, int) else out.data_ptr()
+    return lib().lnf_filter_points(h, vp, _dims_t(*[int(v) for v in dims]), dtype, radius, xp,
+                                   int(n), op, stream_ptr(stream))

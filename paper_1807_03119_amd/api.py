@@ -59,6 +59,18 @@ class Filter:
             raise LnfError(rc, "lnf_filter_otsu")
         return out, t
 
+    def points(self, vol, radius: int, xyz, stream=None):
+        """Filtered values at voxels xyz (int32 [n, 3] device tensor of (x, y, z))."""
+        import torch
+        _require_cuda(vol, "vol")
+        xyz = xyz.to(device=vol.device, dtype=torch.int32).contiguous()
+        out = torch.empty(xyz.shape[0], dtype=torch.int32, device=vol.device)  # uint32 bits
+        rc = _lib.lnf_filter_points(self._h, vol, _lib.dims_of(vol), _lib.dtype_code(vol),
+                                    int(radius), xyz, xyz.shape[0], out, stream)
+        if rc != _lib.LNF_OK:
+            raise LnfError(rc, "lnf_filter_points")
+        return out
+
     def histogram(self, vol, stream=None):
         import torch
         _require_cuda(vol, "vol")
