@@ -25,7 +25,10 @@
  * ((z*ny + y)*nx + x) * sizeof(element).  dims[] = {nx, ny, nz}.
  *
  * All functions return LNF_OK (0) or a negative LNF_E* code and never throw or
- * abort across the ABI.  Work is enqueued asynchronously on the given stream;
+ * abort across the ABI.  Device pointers are checked against the device
+ * allocation that contains them (a region past its end is rejected); a buffer
+ * carved out of a larger allocation by a caching allocator cannot be checked
+ * more finely, so the caller guarantees that each buffer holds what its dims say.  Work is enqueued asynchronously on the given stream;
  * device-side faults surface at the caller's next synchronisation.
  */
 #ifndef LNF_H

@@ -102,10 +102,10 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
     };
 
     const int xq = tid % TX;
-    const int xrow = tid / S::NSEG, xseg = tid % S::NSEG;
-    const bool xactive = xrow < (NARROW ? S::LY / 2 : S::LY);
+    // surplus threads (beyond the last row) redo the last row and write the same
+    // values, so the x-pass needs no divergent branch
+    const int xrow = min(tid / S::NSEG, (NARROW ? S::LY / 2 : S::LY) - 1), xseg = tid % S::NSEG;
     auto xpass = [&](int buf) {
-        if (!xactive) return;
         if constexpr (NARROW) {
             // rows 2*xrow and 2*xrow+1, packed as (low, high) 16-bit halves
             u16x2 wp[S::SW], c[S::SW];
@@ -197,7 +197,28 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
         for (int u = 0; u < D; ++u) pr[u][m] = qr[u][m] = 0;
     }
 
+    // The y-pass of the first iteration reads px/qx buffer 1 before any x-pass
+    // wrote it; zeros there push zeros into the (zero) ring, so the loop body
+    // needs no branch around the y-pass.  Likewise the x-pass and the staging
+    // run in every iteration (the extra ones at the end read clamped slices and
+    // their results are never used).  The loop body is then one basic block the
+    // compiler can interleave; only the stores are conditional, and they are
+    // issued at the top of the next iteration so their latency overlaps work.
+    for (int i = tid; i < S::LY * PXP; i += S::THREADS) {
+        sm.px[1][i] = 0;
+        sm.qx[1][i] = 0;
+    }
     const int ns = (z1 - z0) + 2 * H;  // input slices z0-2r .. z1-1+2r
+    uint32_t opend[YO];
+    int zpend = -1;  // output slice whose values wait in opend, or -1
+    auto flush = [&]() {
+        if (zpend >= 0) {
+            const rsrc_t wr = make_rsrc(out + (size_t)zpend * plane, pbytes);
+#pragma unroll
+            for (int m = 0; m < YO; ++m)
+                if (ok[m]) buffer_store<T>(opend[m], wr, voff, (uint32_t)m * rowb);
+        }
+    };
     stage(z0 - H, 0);
     wait_vmem();
     __syncthreads();
@@ -206,54 +227,45 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
         for (int u = 0; u < D; ++u) {
             const int k = kb + u;  // x-pass of slice k, y-pass of slice k-1
             if (k > ns) break;
+            flush();
             const int buf = u & 1;  // == k & 1 because D is even
-            // y-pass, ring and stores of slice k-1 first, so the stores are on
-            // their way before this iteration's wait
-            if (k >= 1) {
-                const int pb = buf ^ 1;
-                uint32_t cp[S::NPV], cq[S::NQV], qc[YO];
-                cp[0] = xval(pb, false, yg * YO + R);
+            const int pb = buf ^ 1;
+            uint32_t cp[S::NPV], cq[S::NQV], qc[YO];
+            cp[0] = xval(pb, false, yg * YO + R);
 #pragma unroll
-                for (int i = 1; i < S::NPV; ++i) cp[i] = cp[i - 1] + xval(pb, false, yg * YO + R + i);
-                {
-                    uint32_t qv[S::NQV];
+            for (int i = 1; i < S::NPV; ++i) cp[i] = cp[i - 1] + xval(pb, false, yg * YO + R + i);
+            {
+                uint32_t qv[S::NQV];
 #pragma unroll
-                    for (int i = 0; i < S::NQV; ++i) qv[i] = xval(pb, true, yg * YO + i);
-                    cq[0] = qv[0];
+                for (int i = 0; i < S::NQV; ++i) qv[i] = xval(pb, true, yg * YO + i);
+                cq[0] = qv[0];
 #pragma unroll
-                    for (int i = 1; i < S::NQV; ++i) cq[i] = cq[i - 1] + qv[i];
+                for (int i = 1; i < S::NQV; ++i) cq[i] = cq[i - 1] + qv[i];
 #pragma unroll
-                    for (int m = 0; m < YO; ++m) qc[m] = qv[m + 2 * R];
-                }
-                const int uj = (u + D - 1) % D;  // ring slot of slice j = k-1
-#pragma unroll
-                for (int m = 0; m < YO; ++m) {
-                    const uint32_t P = cp[m + 2 * R] - (m ? cp[m - 1] : 0u);
-                    const uint32_t Q = cq[m + 4 * R] - (m ? cq[m - 1] : 0u) + qc[m];
-                    bacc[m] += pr[(uj + D - R) % D][m] - pr[(uj + R + 1) % D][m];
-                    wacc[m] += Q - qr[(uj + 1) % D][m];
-                    pr[uj][m] = P;
-                    qr[uj][m] = Q;
-                }
-                const int j = k - 1;
-                if (j >= 2 * H) {
-                    const int z = z0 + j - 2 * H;
-                    const rsrc_t wr = make_rsrc(out + (size_t)z * plane, pbytes);
-#pragma unroll
-                    for (int m = 0; m < YO; ++m) {
-                        const uint32_t Ssum = bacc[m] + wacc[m] + qr[(uj + D - 2 * R) % D][m];
-                        uint32_t o = round_div_odd(Ssum, inv9n);
-                        if (GATE && o < gate) o = 0;
-                        if (ok[m]) buffer_store<T>(o, wr, voff, (uint32_t)m * rowb);
-                    }
-                }
+                for (int m = 0; m < YO; ++m) qc[m] = qv[m + 2 * R];
             }
-            if (k + 1 < ns) stage(z0 - H + k + 1, buf ^ 1);
-            if (k < ns) xpass(buf);
+            const int uj = (u + D - 1) % D;  // ring slot of slice j = k-1
+#pragma unroll
+            for (int m = 0; m < YO; ++m) {
+                const uint32_t P = cp[m + 2 * R] - (m ? cp[m - 1] : 0u);
+                const uint32_t Q = cq[m + 4 * R] - (m ? cq[m - 1] : 0u) + qc[m];
+                bacc[m] += pr[(uj + D - R) % D][m] - pr[(uj + R + 1) % D][m];
+                wacc[m] += Q - qr[(uj + 1) % D][m];
+                pr[uj][m] = P;
+                qr[uj][m] = Q;
+                const uint32_t Ssum = bacc[m] + wacc[m] + qr[(uj + D - 2 * R) % D][m];
+                uint32_t o = round_div_odd(Ssum, inv9n);
+                if (GATE && o < gate) o = 0;
+                opend[m] = o;
+            }
+            zpend = (k - 1 >= 2 * H) ? z0 + k - 1 - 2 * H : -1;
+            stage(z0 - H + k + 1, buf ^ 1);
+            xpass(buf);
             wait_vmem();
             __syncthreads();
         }
     }
+    flush();
 }
 
 }  // namespace lnf

@@ -15,7 +15,8 @@
 //   1. stage the raw (32+4r) x (8+4r) slice tile in LDS (loads of slice k+1
 //      are issued into registers before slice k is processed);
 //   2. x-pass: box sums of E and E^2 over 2r+1 columns for every cluster-centre
-//      column of the (32+2r) wide region, on all 8+4r rows;
+//      column of the (32+2r) wide region, on all 8+4r rows, as prefix-sum
+//      differences over 8-wide row segments;
 //   3. y-pass + z-window: each thread owns up to NCI centre columns of the
 //      (32+2r) x (8+2r) region; it forms the 2D box sums and keeps a register
 //      ring of the last 2r+1 of them to slide box_z, and writes the finished
@@ -39,7 +40,10 @@ struct MV9Shape {
     static constexpr int NLOAD = (NRAW + THREADS - 1) / THREADS;
     static constexpr int NFULL = NRAW / THREADS;
     static constexpr int NXP = LY * GX;
-    static constexpr int NXI = (NXP + THREADS - 1) / THREADS;
+    static constexpr int XS = 8;                           // x-pass positions per thread
+    static constexpr int NXS = (GX + XS - 1) / XS;         // x-pass segments per row
+    static constexpr int LXP = NXS * XS + 2 * R;           // raw row pitch (tail padded)
+    static_assert(LY * NXS <= THREADS, "x-pass: one thread per row segment");
     static constexpr int NCOL = GX * GY;
     static constexpr int NCI = (NCOL + THREADS - 1) / THREADS;
     static constexpr int P = 2 * R + 1;  // ring period and number of planes
@@ -51,7 +55,7 @@ struct MV9Smem {
     using S = MV9Shape<R>;
     double qx[S::NXP];
     double bq[S::P][S::NCOL];
-    uint32_t raw[S::NRAW];
+    uint32_t raw[S::LY * S::LXP];
     uint32_t bx[S::NXP];
     uint32_t bs[S::P][S::NCOL];
 };
@@ -69,12 +73,14 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R>& sm, const T* __restrict
     const uint32_t pbytes = (uint32_t)(plane * sizeof(T));
 
     uint32_t off[S::NLOAD];
+    int lidx[S::NLOAD];  // padded LDS index of each staged element
 #pragma unroll
     for (int i = 0; i < S::NLOAD; ++i) {
         const int e = min(tid + i * kThreads, S::NRAW - 1);
         const int row = e / LX, col = e - row * LX;
         off[i] = (uint32_t)(clampi(y0 - H + row, 0, g.ny - 1) * g.nx +
                             clampi(x0 - H + col, 0, g.nx - 1)) * (uint32_t)sizeof(T);
+        lidx[i] = row * S::LXP + col;
     }
     const bool last_ok = tid + (S::NLOAD - 1) * kThreads < S::NRAW;
     uint32_t v[S::NLOAD];
@@ -99,6 +105,12 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R>& sm, const T* __restrict
         }
     }
 
+    // the tail of each padded raw row is read by the last x-pass segment but
+    // only feeds discarded positions; keep it defined
+    if constexpr (S::LXP > LX) {
+        constexpr int PAD = S::LXP - LX;
+        for (int i = tid; i < S::LY * PAD; i += kThreads) sm.raw[(i / PAD) * S::LXP + LX + i % PAD] = 0;
+    }
     const int ox = tid % TX, oy = tid / TX;
     const int ns = (z1 - z0) + 2 * H;
     load(z0 - H);
@@ -110,27 +122,35 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R>& sm, const T* __restrict
             // 1. stage
 #pragma unroll
             for (int i = 0; i < S::NLOAD; ++i)
-                if (i < S::NFULL || last_ok) sm.raw[tid + i * kThreads] = v[i];
+                if (i < S::NFULL || last_ok) sm.raw[lidx[i]] = v[i];
             if (k + 1 < ns) load(z0 - H + k + 1);
             __syncthreads();
 
-            // 2. x-pass: centre column c of the region is raw column c + r
+            // 2. x-pass: centre column c of the region is raw column c + r; each
+            //    thread runs prefix sums over an 8-wide segment (+2r halo)
+            {
+                const int row = tid / S::NXS, seg = tid % S::NXS;
+                if (row < S::LY) {
+                    constexpr int W = S::XS + 2 * R;
+                    const uint32_t* rp = sm.raw + row * S::LXP + seg * S::XS;
+                    uint32_t cb[W];
+                    double cq[W];
+                    cb[0] = rp[0];
+                    cq[0] = (double)rp[0] * (double)rp[0];
 #pragma unroll
-            for (int j = 0; j < S::NXI; ++j) {
-                const int it = tid + j * kThreads;
-                if (it < S::NXP) {
-                    const int row = it / GX, col = it - row * GX;
-                    const uint32_t* rp = sm.raw + row * LX + col;
-                    uint32_t b = 0;
-                    double q = 0.0;
-#pragma unroll
-                    for (int t = 0; t <= 2 * R; ++t) {
-                        const uint32_t e = rp[t];
-                        b += e;
-                        q = __builtin_fma((double)e, (double)e, q);
+                    for (int i = 1; i < W; ++i) {
+                        const uint32_t e = rp[i];
+                        cb[i] = cb[i - 1] + e;
+                        cq[i] = __builtin_fma((double)e, (double)e, cq[i - 1]);
                     }
-                    sm.bx[it] = b;
-                    sm.qx[it] = q;
+#pragma unroll
+                    for (int m = 0; m < S::XS; ++m) {
+                        const int c = seg * S::XS + m;
+                        if (c < GX) {
+                            sm.bx[row * GX + c] = cb[m + 2 * R] - (m ? cb[m - 1] : 0u);
+                            sm.qx[row * GX + c] = cq[m + 2 * R] - (m ? cq[m - 1] : 0.0);
+                        }
+                    }
                 }
             }
             __syncthreads();

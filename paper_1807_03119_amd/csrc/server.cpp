@@ -469,7 +469,8 @@ private:
         int rc = LNF_OK;
         if (o_.fail_batch > 0 && batches_ == (uint64_t)o_.fail_batch) rc = LNF_ECANCELED;
         if (rc == LNF_OK) {
-            if (o_.mode == LNF_SERVE_FIFO)
+            // a micro-batch of one is a plain launch: no table upload, no graph
+            if (o_.mode == LNF_SERVE_FIFO || jobs.size() == 1)
                 rc = lnf_filter(h_, jobs[0].in, jobs[0].dims, jobs[0].dtype, jobs[0].radius,
                                 jobs[0].out, s);
             else
