@@ -81,6 +81,29 @@ __device__ __forceinline__ void buffer_load_lds<uint16_t>(rsrc_t r, void* dst_wa
 // Wait for this wave's outstanding vector-memory operations (including LDS DMA).
 __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Workgroup barrier that orders LDS traffic only.  __syncthreads() also
+// fences global memory, which makes every wave wait for all its outstanding
+// loads and stores (vmcnt 0) first; here only this wave's LDS operations are
+// waited for, so global loads, stores and LDS DMA stay in flight across it.
+// The empty asm statements keep the compiler from moving memory accesses
+// across the barrier.
+__device__ __forceinline__ void barrier_lds()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Wait until at most N of this wave's vector-memory operations are outstanding.
+// They retire in issue order (loads, stores and LDS DMA alike), so every
+// operation issued before the last N has then completed.
+template <int N>
+__device__ __forceinline__ void wait_vmem_le()
+{
+    static_assert(N >= 0 && N <= 63, "vmcnt is a 6-bit counter");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
 // round(S / d) for an odd divisor d, as trunc(S * (1/d) + 1/2) in fp64.
 // (2S + d) / (2d) is never an integer (odd over even), so it lies at least
 // 1/(2d) from every integer, while the fp64 error is below 2^-52 * S/d; with

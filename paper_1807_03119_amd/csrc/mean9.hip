@@ -207,8 +207,8 @@ struct Variant {
 };
 // 0: first design (two barriers per slice, register staging)
 // 1-4: LDS-DMA staging, double buffering, one barrier per slice; 64 or 32 wide
-constexpr Variant kVariants[] = {{64, 16, 256, 1024}, {64, 16, 256, 1024}, {64, 32, 512, 512},
-                                 {32, 16, 128, 2048}, {32, 32, 256, 1024}};
+constexpr Variant kVariants[] = {{64, 16, 256, 1024}, {64, 16, 256, 512}, {64, 32, 512, 256},
+                                 {32, 16, 128, 1024}, {32, 32, 256, 512}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kDefaultVariant = 1;
 

@@ -9,9 +9,10 @@
 //
 // Pipeline per input slice k (one barrier per slice; stages listed in the
 // order they are issued within one iteration):
-//   - LDS DMA: the raw (TX+4r) x (TY+4r) tile of slice k+1 is loaded straight
+//   - LDS DMA: the raw (TX+4r) x (TY+4r) tile of slice k+PF is loaded straight
 //     from HBM into LDS (one element per lane, zero-extended to 32 bits), its
-//     coordinates clamped into the volume per lane;
+//     coordinates clamped into the volume per lane; PF+1 raw buffers form a
+//     ring, so each slice has PF iterations to arrive;
 //   - x-pass of slice k: each thread takes an 8-wide row segment, forms prefix
 //     sums over its 8+4r raw values and writes px = box_x E and qx = c_x E;
 //   - y-pass of slice k-1: each thread owns one column and four rows, forms
@@ -19,9 +20,13 @@
 //     register ring of the last 4r+2 slices; the ring keeps the running sums
 //     B = sum of P over [z-r, z+r] and W = sum of Q over [z-2r, z+2r] for the
 //     output slice z, two r behind the newest slice, and S = B + W + Q(z);
-//   - out = round(S / 9n) (fp64, exact), gate, store.
-// raw, px and qx are double-buffered, so the x-pass of slice k overlaps the
-// y-pass of slice k-1 and the DMA of slice k+1.
+//   - out = round(S / 9n) (fp64, exact), gate, store (issued at the top of
+//     the next iteration).
+// px and qx are double-buffered, so the x-pass of slice k overlaps the y-pass
+// of slice k-1.  Every iteration issues exactly NLOAD loads and YO stores (no
+// branch around any of them: masked-off stores go to an offset the buffer's
+// range check drops), so the wait for slice k+1 at the end of iteration k is
+// a partial one that leaves the younger PF-1 iterations' operations in flight.
 #pragma once
 
 #include "device_common.h"
@@ -38,21 +43,38 @@ __device__ __forceinline__ u16x2 pack16(uint32_t lo, uint32_t hi)
 
 __device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 
+#ifndef LNF_M9_PREFETCH
+#define LNF_M9_PREFETCH 2
+#endif
+
 template <int R, int TY, int TXW = 64>
 struct M9Shape {
     static constexpr int TX = TXW;
     static constexpr int YO = 4;                    // output rows per thread
     static constexpr int THREADS = TX * TY / YO;    // one thread per column x YO rows
     static constexpr int H = 2 * R;                 // halo: cluster radius + offset
-    static constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
+    // Raw row pitch: the 4r-column halo plus padding to 4 mod 8 words, so that
+    // eight consecutive rows start in eight different groups of four LDS banks
+    // (the x-pass reads 16 bytes per lane, eight lanes per bank cycle).  The
+    // padding columns are loaded like halo (clamped) and never used.
+    static constexpr int LX = (TX + 4 * R) % 8 == 4 ? TX + 4 * R : TX + 4 * R + 4;
+    static constexpr int LY = TY + 2 * H;
     static constexpr int NRAW = LX * LY;
     static constexpr int NLOAD = (NRAW + THREADS - 1) / THREADS;
     static constexpr int NFULL = NRAW / THREADS;
     static constexpr int PXP = TX + 4;              // padded px/qx row pitch (words)
     static constexpr int D = 4 * R + 2;             // ring period (even)
     static constexpr int SEG = 8, NSEG = TX / SEG, SW = SEG + 4 * R;
+    static constexpr int XRW = (LY + 7) / 8 * 8;        // x-pass row slots, wide path
+    static constexpr int XRN = (LY / 2 + 7) / 8 * 8;    // x-pass row-pair slots, narrow path
     static constexpr int NPV = YO + 2 * R, NQV = YO + 4 * R;
-    static_assert(LY * NSEG <= THREADS, "x-pass: one thread per row segment");
+    static constexpr int PF = LNF_M9_PREFETCH;       // slices staged ahead of the x-pass
+    static constexpr int NRB = PF + 1;               // raw slice buffers (a ring)
+    // vector-memory operations issued after a slice's loads, up to the wait
+    // that needs that slice: PF-1 iterations of (NLOAD loads + YO stores)
+    static constexpr int VMWAIT = (PF - 1) * (NLOAD + YO);
+    static_assert(PF >= 1 && VMWAIT <= 63, "prefetch depth out of range");
+    static_assert(XRW * NSEG <= THREADS, "x-pass: one thread per row segment");
     static_assert(D % 2 == 0, "buffer parity must be static in the unrolled ring");
     static_assert(LX % 4 == 0, "x-pass reads 16-byte aligned rows");
 };
@@ -60,7 +82,7 @@ struct M9Shape {
 template <int R, int TY, int TXW = 64>
 struct M9Smem {
     using S = M9Shape<R, TY, TXW>;
-    uint32_t raw[2][S::NLOAD * S::THREADS];
+    uint32_t raw[S::NRB][S::NLOAD * S::THREADS];
     uint32_t px[2][S::LY * S::PXP];
     uint32_t qx[2][S::LY * S::PXP];
 };
@@ -91,25 +113,28 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
         const int gx = clampi(x0 - H + col, 0, g.nx - 1);
         off[i] = (uint32_t)(gy * g.nx + gx) * (uint32_t)sizeof(T);
     }
-    const bool last_ok = tid + (S::NLOAD - 1) * S::THREADS < S::NRAW;
-
-    auto stage = [&](int zi, int buf) {
+    // every lane issues all NLOAD loads (lanes past the tile reload its last
+    // element into unused LDS words), so the count per stage is fixed
+    auto stage = [&](int zi, int slot) {
         const rsrc_t rs = make_rsrc(in + (size_t)clampi(zi, 0, g.nz - 1) * plane, pbytes);
 #pragma unroll
         for (int i = 0; i < S::NLOAD; ++i)
-            if (i < S::NFULL || last_ok)
-                buffer_load_lds<T>(rs, &sm.raw[buf][i * S::THREADS + wave * 64], off[i]);
+            buffer_load_lds<T>(rs, &sm.raw[slot][i * S::THREADS + wave * 64], off[i]);
     };
 
     const int xq = tid % TX;
-    // surplus threads (beyond the last row) redo the last row and write the same
-    // values, so the x-pass needs no divergent branch
-    const int xrow = min(tid / S::NSEG, (NARROW ? S::LY / 2 : S::LY) - 1), xseg = tid % S::NSEG;
-    auto xpass = [&](int buf) {
+    // x-pass mapping: consecutive lanes take consecutive rows of one segment
+    // (bank-conflict free with the padded pitch).  Row slots are padded to a
+    // multiple of 8; surplus lanes and threads redo the last row or segment and
+    // write the same values, so the x-pass needs no divergent branch.
+    constexpr int XR = NARROW ? S::XRN : S::XRW;
+    const int xrow = min(tid % XR, (NARROW ? S::LY / 2 : S::LY) - 1);
+    const int xseg = min(tid / XR, S::NSEG - 1);
+    auto xpass = [&](int buf, int slot) {
         if constexpr (NARROW) {
             // rows 2*xrow and 2*xrow+1, packed as (low, high) 16-bit halves
             u16x2 wp[S::SW], c[S::SW];
-            const uint32_t* r0 = sm.raw[buf] + (2 * xrow) * LX + xseg * S::SEG;
+            const uint32_t* r0 = sm.raw[slot] + (2 * xrow) * LX + xseg * S::SEG;
             const uint32_t* r1 = r0 + LX;
 #pragma unroll
             for (int i = 0; i < S::SW; i += 4) {
@@ -142,7 +167,7 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
             return;
         }
         uint32_t w[S::SW], c[S::SW];
-        const uint32_t* rp = sm.raw[buf] + xrow * LX + xseg * S::SEG;
+        const uint32_t* rp = sm.raw[slot] + xrow * LX + xseg * S::SEG;
 #pragma unroll
         for (int i = 0; i < S::SW; i += 4) {
             const uint4 t4 = *reinterpret_cast<const uint4*>(rp + i);
@@ -185,9 +210,12 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
     const int xo = x0 + xq, ybase = y0 + yg * YO;
     const uint32_t voff = (uint32_t)((size_t)ybase * g.nx + xo) * (uint32_t)sizeof(T);
     const uint32_t rowb = (uint32_t)g.nx * (uint32_t)sizeof(T);
-    bool ok[YO];
+    // per-row store offsets; rows or columns outside the volume get the plane
+    // size, which the range check of the store's buffer resource drops
+    uint32_t soff[YO];
 #pragma unroll
-    for (int m = 0; m < YO; ++m) ok[m] = xo < g.nx && ybase + m < g.ny;
+    for (int m = 0; m < YO; ++m)
+        soff[m] = (xo < g.nx && ybase + m < g.ny) ? voff + (uint32_t)m * rowb : pbytes;
 
     uint32_t pr[D][YO], qr[D][YO], bacc[YO], wacc[YO];
 #pragma unroll
@@ -210,18 +238,26 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
     }
     const int ns = (z1 - z0) + 2 * H;  // input slices z0-2r .. z1-1+2r
     uint32_t opend[YO];
-    int zpend = -1;  // output slice whose values wait in opend, or -1
-    auto flush = [&]() {
-        if (zpend >= 0) {
-            const rsrc_t wr = make_rsrc(out + (size_t)zpend * plane, pbytes);
 #pragma unroll
-            for (int m = 0; m < YO; ++m)
-                if (ok[m]) buffer_store<T>(opend[m], wr, voff, (uint32_t)m * rowb);
-        }
+    for (int m = 0; m < YO; ++m) opend[m] = 0;
+    int zpend = -1;  // output slice whose values wait in opend, or -1
+    // stores of opend; with no pending slice they go to an empty buffer
+    // resource (every access dropped), so each call issues exactly YO stores
+    auto flush = [&]() {
+        const rsrc_t wr = make_rsrc(out + (size_t)max(zpend, 0) * plane, zpend >= 0 ? pbytes : 0u);
+#pragma unroll
+        for (int m = 0; m < YO; ++m) buffer_store<T>(opend[m], wr, soff[m], 0u);
     };
+    // prologue: slices 0 .. PF-1, each but the first preceded by YO (dropped)
+    // stores so the operation pattern matches the loop's
     stage(z0 - H, 0);
-    wait_vmem();
-    __syncthreads();
+#pragma unroll
+    for (int p = 1; p < S::PF; ++p) {
+        flush();
+        stage(z0 - H + p, p);
+    }
+    wait_vmem_le<S::VMWAIT>();
+    barrier_lds();
     for (int kb = 0; kb <= ns; kb += D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) {
@@ -259,13 +295,18 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
                 opend[m] = o;
             }
             zpend = (k - 1 >= 2 * H) ? z0 + k - 1 - 2 * H : -1;
-            stage(z0 - H + k + 1, buf ^ 1);
-            xpass(buf);
-            wait_vmem();
-            __syncthreads();
+            // slice i lives in raw slot i mod NRB: slice k+PF takes the slot
+            // slice k-1 used, read in the previous iteration
+            stage(z0 - H + k + S::PF, (k + S::PF) % S::NRB);
+            xpass(buf, k % S::NRB);
+            wait_vmem_le<S::VMWAIT>();  // slice k+1 has landed
+            barrier_lds();
         }
     }
     flush();
+    // drain the staging of the slices past the end before the LDS is reused
+    wait_vmem();
+    barrier_lds();
 }
 
 }  // namespace lnf

@@ -13,7 +13,8 @@
 //
 // Per input slice:
 //   1. stage the raw (32+4r) x (8+4r) slice tile in LDS (loads of slice k+1
-//      are issued into registers before slice k is processed);
+//      are issued into registers before slice k is processed, and stay in
+//      flight across the slice's LDS-only barriers);
 //   2. x-pass: box sums of E and E^2 over 2r+1 columns for every cluster-centre
 //      column of the (32+2r) wide region, on all 8+4r rows, as prefix-sum
 //      differences over 8-wide row segments;
@@ -124,7 +125,7 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R>& sm, const T* __restrict
             for (int i = 0; i < S::NLOAD; ++i)
                 if (i < S::NFULL || last_ok) sm.raw[lidx[i]] = v[i];
             if (k + 1 < ns) load(z0 - H + k + 1);
-            __syncthreads();
+            barrier_lds();
 
             // 2. x-pass: centre column c of the region is raw column c + r; each
             //    thread runs prefix sums over an 8-wide segment (+2r halo)
@@ -153,7 +154,7 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R>& sm, const T* __restrict
                     }
                 }
             }
-            __syncthreads();
+            barrier_lds();
 
             // 3. y-pass + z-window; region row gy covers x-pass rows gy .. gy+2r
 #pragma unroll
@@ -176,7 +177,7 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R>& sm, const T* __restrict
                     sm.bq[u][it] = qsum[j];
                 }
             }
-            __syncthreads();
+            barrier_lds();
 
             // 4. gather for output slice z = zi - 2r
             if (k >= 2 * H) {
