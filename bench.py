@@ -241,8 +241,6 @@ def main():
     ap.add_argument("--rule", choices=["mean9", "minvar9"], default="mean9")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--data12", action="store_true",
-                    help="declare the phantom's 12-bit range (LNF_FLAG_DATA_12BIT)")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the served-mode trace (0 skips it)")
     args = ap.parse_args()
@@ -263,8 +261,7 @@ def main():
     out = torch.empty_like(vol)
     nvox = vol.numel()
     rule_code = _lib.LNF_MEAN9 if args.rule == "mean9" else _lib.LNF_MINVAR9
-    flags = _lib.LNF_FLAG_DATA_12BIT if args.data12 else 0
-    f = Filter(rule_code, 0, flags=flags)
+    f = Filter(rule_code, 0)
 
     def step():
         f(vol, args.radius, out=out)
@@ -283,8 +280,7 @@ def main():
         "config": {"workload": f"single {DIMS[0]}x{DIMS[1]}x{DIMS[2]} uint16 (12-bit) CT "
                                f"phantom, radius {args.radius}, {args.rule.upper()}",
                    "dims": list(DIMS), "voxel": "uint16", "radius": args.radius,
-                   "rule": args.rule.upper(), "seed": SEED,
-                   "flags": "LNF_FLAG_DATA_12BIT" if args.data12 else "none"},
+                   "rule": args.rule.upper(), "seed": SEED},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "timed_wall_s": wall,

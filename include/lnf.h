@@ -75,20 +75,14 @@ typedef struct {
     int32_t rule;     /* LNF_MEAN9 (default) or LNF_MINVAR9 */
     uint32_t gate_T;  /* data threshold T of the noise gate; 0 disables the gate */
     int32_t device;   /* HIP device ordinal; -1 = the device current at create time */
-    uint32_t flags;   /* LNF_FLAG_* bits, 0 = none */
+    uint32_t flags;   /* reserved, must be 0 */
 } lnf_options;
-
-/* The caller guarantees that every uint16 voxel value is below 4096 (12-bit CT
- * data).  The MEAN9 kernels may then keep x-pass sums in 16 bits for r <= 3.
- * Larger values give unspecified output values (never an out-of-bounds
- * access).  uint8 volumes need no flag. */
-#define LNF_FLAG_DATA_12BIT 1u
 
 /*
  * Create a filter context.  opt == NULL gives the defaults (LNF_MEAN9, gate off,
  * current device).  Allocates only library-internal state (a few KB of device
  * memory for the batch descriptor table and the histogram scratch).
- * Errors: LNF_EINVAL (h NULL, bad rule, unknown flags, size), LNF_EDEVICE (bad device),
+ * Errors: LNF_EINVAL (h NULL, bad rule, nonzero flags, size), LNF_EDEVICE (bad device),
  * LNF_ENOMEM, LNF_EHIP.
  */
 LNF_API int lnf_create(lnf_handle* h, const lnf_options* opt);

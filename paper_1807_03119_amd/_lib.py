@@ -28,7 +28,6 @@ LNF_U16 = 2
 LNF_MEAN9 = 0
 LNF_MINVAR9 = 1
 LNF_RADIUS_MAX = 4
-LNF_FLAG_DATA_12BIT = 1
 
 
 class LnfError(RuntimeError):

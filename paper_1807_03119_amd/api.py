@@ -21,12 +21,11 @@ def _require_cuda(t, name):
 class Filter:
     """One lnf context: a rule and a gate threshold on one device."""
 
-    def __init__(self, rule: int = LNF_MEAN9, gate: int = 0, device: int | None = None,
-                 flags: int = 0):
+    def __init__(self, rule: int = LNF_MEAN9, gate: int = 0, device: int | None = None):
         import torch
         dev = torch.cuda.current_device() if device is None else int(device)
-        self.rule, self.gate, self.device, self.flags = rule, int(gate), dev, int(flags)
-        self._h = _lib.lnf_create(rule, int(gate), dev, int(flags))
+        self.rule, self.gate, self.device = rule, int(gate), dev
+        self._h = _lib.lnf_create(rule, int(gate), dev)
 
     @property
     def handle(self):

@@ -3,10 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 
@@ -23,6 +25,44 @@ int default_zs(int tiles_xy, int nz, int target_groups)
     const int max_nzs = std::max(1, (nz + kMinDepth - 1) / kMinDepth);
     nzs = std::min(std::max(nzs, 1), max_nzs);
     return (nz + nzs - 1) / nzs;
+}
+
+int resident_groups(const void* kernel, int threads)
+{
+    constexpr int kMaxDev = 64;
+    static std::atomic<int> cus[kMaxDev];  // CU count per device, 0 = not queried yet
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> per_cu;  // resident groups per CU
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) {
+        (void)hipGetLastError();
+        return 1024;
+    }
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n <= 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n <= 0) {
+            (void)hipGetLastError();
+            n = 256;
+        }
+        cus[dev].store(n, std::memory_order_relaxed);
+    }
+    int k = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = per_cu.find({kernel, threads});
+        if (it != per_cu.end()) {
+            k = it->second;
+        } else {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, kernel, threads, 0) != hipSuccess ||
+                k <= 0) {
+                (void)hipGetLastError();
+                k = 2;
+            }
+            per_cu[{kernel, threads}] = k;
+        }
+    }
+    return n * k;
 }
 
 int check_volume_args(const lnf_ctx* h, const void* vol, const int64_t dims[3], int dtype,
@@ -92,10 +132,9 @@ TileCfg ctx_tile(const lnf_ctx* h, int rule, int dtype, int radius, Geom g)
 }
 
 hipError_t launch_rule(int rule, const void* in, void* out, int dtype, int r, Geom g,
-                       uint32_t gate, TileCfg cfg, hipStream_t s, uint32_t flags)
+                       uint32_t gate, TileCfg cfg, hipStream_t s)
 {
-    if (rule == LNF_MEAN9)
-        return launch_mean9(in, out, dtype, r, g, gate, cfg, s, mean9_narrow(dtype, r, flags));
+    if (rule == LNF_MEAN9) return launch_mean9(in, out, dtype, r, g, gate, cfg, s);
     return launch_minvar9(in, out, dtype, r, g, gate, cfg, s);
 }
 
@@ -156,7 +195,7 @@ int lnf_create(lnf_handle* h, const lnf_options* opt)
         o = *opt;
     }
     if (o.rule != LNF_MEAN9 && o.rule != LNF_MINVAR9) return LNF_EINVAL;
-    if (o.flags & ~LNF_FLAG_DATA_12BIT) return LNF_EINVAL;
+    if (o.flags != 0) return LNF_EINVAL;  // no flags are defined
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         (void)hipGetLastError();
@@ -170,7 +209,6 @@ int lnf_create(lnf_handle* h, const lnf_options* opt)
     c->device = dev;
     c->rule = o.rule;
     c->gate = o.gate_T;
-    c->flags = o.flags;
     const int rc = ctx_init_device_state(c);
     if (rc != LNF_OK) {
         delete c;
@@ -219,7 +257,7 @@ int lnf_filter_tiled(lnf_handle h, const void* vol, const int64_t dims[3], int d
     if (!dg.ok()) return LNF_EHIP;
     if ((rc = check_device_range(vol, bytes, h->device))) return rc;
     if ((rc = check_device_range(out, bytes, h->device))) return rc;
-    if (launch_rule(h->rule, vol, out, dtype, radius, g, h->gate, cfg, stream, h->flags) !=
+    if (launch_rule(h->rule, vol, out, dtype, radius, g, h->gate, cfg, stream) !=
         hipSuccess)
         return LNF_EHIP;
     return LNF_OK;

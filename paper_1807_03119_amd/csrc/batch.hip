@@ -81,8 +81,7 @@ __device__ __forceinline__ bool next_tile(BatchTable* tab, BatchQueue* q, int* s
 
 template <int R, bool GATE>
 __global__ __launch_bounds__((M9Shape<R, kMean9TY>::THREADS)) void mean9_batch(BatchTable* tab,
-                                                                             uint32_t gate,
-                                                                             int narrow16)
+                                                                             uint32_t gate)
 {
     __shared__ __align__(16) M9Smem<R, kMean9TY> sm;
     __shared__ int s_tile, s_job;
@@ -99,30 +98,18 @@ __global__ __launch_bounds__((M9Shape<R, kMean9TY>::THREADS)) void mean9_batch(B
         const int bz = rest / d.tiles_y;
         const Geom g{d.nx, d.ny, d.nz};
         const int z0 = bz * d.zs, z1 = min(z0 + d.zs, d.nz);
-        if (d.dtype == LNF_U8) {
-            mean9_tile<R, kMean9TY, uint8_t, GATE, 64, true>(sm, (const uint8_t*)d.in,
-                                                             (uint8_t*)d.out, g, bx * 64,
-                                                             by * kMean9TY, z0, z1, gate, inv9n);
-        } else {
-            bool done = false;
-            if constexpr (R <= 3) {
-                if (narrow16) {
-                    mean9_tile<R, kMean9TY, uint16_t, GATE, 64, true>(
-                        sm, (const uint16_t*)d.in, (uint16_t*)d.out, g, bx * 64, by * kMean9TY,
-                        z0, z1, gate, inv9n);
-                    done = true;
-                }
-            }
-            if (!done)
-                mean9_tile<R, kMean9TY, uint16_t, GATE>(sm, (const uint16_t*)d.in,
-                                                        (uint16_t*)d.out, g, bx * 64,
-                                                        by * kMean9TY, z0, z1, gate, inv9n);
-        }
+        if (d.dtype == LNF_U8)
+            mean9_tile<R, kMean9TY, uint8_t, GATE>(sm, (const uint8_t*)d.in, (uint8_t*)d.out, g,
+                                                   bx * 64, by * kMean9TY, z0, z1, gate, inv9n);
+        else
+            mean9_tile<R, kMean9TY, uint16_t, GATE>(sm, (const uint16_t*)d.in, (uint16_t*)d.out,
+                                                    g, bx * 64, by * kMean9TY, z0, z1, gate,
+                                                    inv9n);
     }
 }
 
 template <int R, bool GATE>
-__global__ __launch_bounds__(256) void minvar9_batch(BatchTable* tab, uint32_t gate, int)
+__global__ __launch_bounds__(256) void minvar9_batch(BatchTable* tab, uint32_t gate)
 {
     __shared__ __align__(16) MV9Smem<R> sm;
     __shared__ int s_tile, s_job;
@@ -148,7 +135,7 @@ __global__ __launch_bounds__(256) void minvar9_batch(BatchTable* tab, uint32_t g
     }
 }
 
-using BatchKernel = void (*)(BatchTable*, uint32_t, int);
+using BatchKernel = void (*)(BatchTable*, uint32_t);
 
 BatchKernel batch_kernel(int rule, int r, bool gate)
 {
@@ -230,8 +217,7 @@ int build_slot(const lnf_ctx* h, BatchState* st, BatchSlot& s)
     for (int r = 1; r <= LNF_RADIUS_MAX; ++r) {
         BatchTable* tab = s.dev;
         uint32_t g = h->gate;
-        int narrow16 = (h->flags & LNF_FLAG_DATA_12BIT) ? 1 : 0;
-        void* args[] = {&tab, &g, &narrow16};
+        void* args[] = {&tab, &g};
         hipKernelNodeParams p{};
         p.func = reinterpret_cast<void*>(batch_kernel(h->rule, r, gate));
         p.gridDim = dim3(st->grid[r - 1]);

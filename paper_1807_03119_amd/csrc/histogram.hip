@@ -249,7 +249,7 @@ extern "C" int lnf_filter_otsu(lnf_handle h, const void* vol, const int64_t dims
     const uint32_t t = otsu_from_hist(h->otsu_host, levels);
     if (T) *T = t;
     if (launch_rule(h->rule, vol, out, dtype, radius, g, t, ctx_tile(h, h->rule, dtype, radius, g),
-                    stream, h->flags) != hipSuccess)
+                    stream) != hipSuccess)
         return LNF_EHIP;
     return LNF_OK;
 }

@@ -25,17 +25,11 @@ struct TileCfg {
 
 // ---- MEAN9 (mean of the nine cluster means) -------------------------------
 int mean9_variants();
-int mean9_default_variant();
+int mean9_default_variant(int dtype, int r);
 // Tile footprint of a variant: output tile width/height in x/y.
 void mean9_tile_shape(int variant, int* tx, int* ty);
-// narrow: x-pass sums fit 16 bits (uint8 data, or 12-bit uint16 data with r <= 3)
 hipError_t launch_mean9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
-                        TileCfg cfg, hipStream_t s, bool narrow);
-// Whether the narrow MEAN9 path is valid for (dtype, r) under the context flags.
-inline bool mean9_narrow(int dtype, int r, uint32_t flags)
-{
-    return dtype == LNF_U8 || ((flags & LNF_FLAG_DATA_12BIT) && r <= 3);
-}
+                        TileCfg cfg, hipStream_t s);
 
 // ---- MINVAR9 (least-variance cluster) -------------------------------------
 int minvar9_variants();
@@ -43,7 +37,11 @@ void minvar9_tile_shape(int variant, int* tx, int* ty);
 hipError_t launch_minvar9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
                           TileCfg cfg, hipStream_t s);
 
-// Default z-strip depth: enough workgroups to give every CU several tiles.
+// Default z-strip depth: nz split into enough strips that tiles_xy * strips
+// reaches target_groups (strips no shallower than 16 slices).
 int default_zs(int tiles_xy, int nz, int target_groups);
+// Workgroups of `kernel` (launched with `threads` threads, no dynamic LDS) that
+// the current device holds at once: CUs x resident workgroups per CU.
+int resident_groups(const void* kernel, int threads);
 
 }  // namespace lnf

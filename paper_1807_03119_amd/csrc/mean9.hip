@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void mean9_ring_64x16(const T* __restrict
 }
 
 // Single-volume wrapper around the streaming tile body of mean9_tile.h.
-template <int R, int TY, typename T, bool GATE, int TXW = 64, bool NARROW = false>
+template <int R, int TY, typename T, bool GATE, int TXW = 64>
 __global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS)) void mean9_stream(
     const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
     int total, uint32_t gate, double inv9n)
@@ -197,106 +197,110 @@ __global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS)) void mean9_stream(
     const int by = rest % tiles_y;
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
-    mean9_tile<R, TY, T, GATE, TXW, NARROW>(sm, in, out, g, bx * TXW, by * TY, z0,
-                                            min(z0 + zs, g.nz), gate, inv9n);
+    mean9_tile<R, TY, T, GATE, TXW>(sm, in, out, g, bx * TXW, by * TY, z0, min(z0 + zs, g.nz),
+                                    gate, inv9n);
 }
 
 struct Variant {
     int tx, ty, threads;
-    int target_groups;  // default z-strip depth aims at this many workgroups
 };
 // 0: first design (two barriers per slice, register staging)
-// 1-4: LDS-DMA staging, double buffering, one barrier per slice; 64 or 32 wide
-constexpr Variant kVariants[] = {{64, 16, 256, 1024}, {64, 16, 256, 512}, {64, 32, 512, 256},
-                                 {32, 16, 128, 1024}, {32, 32, 256, 512}};
+// 1-4: LDS-DMA staging ring, one barrier per slice; 64 or 32 wide, 16 or 32 high
+constexpr Variant kVariants[] = {{64, 16, 256}, {64, 16, 256}, {64, 32, 512}, {32, 16, 128},
+                                 {32, 32, 256}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
-constexpr int kDefaultVariant = 1;
 
-template <int R, typename T, bool GATE, bool NARROW>
-hipError_t launch_variant(int variant, const void* in, void* out, Geom g, uint32_t gate, int zs,
-                          hipStream_t s)
+// Default variant per voxel type and radius (index r-1): the fastest at the
+// default z-strip depth on 512^3 volumes.
+constexpr int kDefaultU16[LNF_RADIUS_MAX] = {2, 1, 1, 3};
+constexpr int kDefaultU8[LNF_RADIUS_MAX] = {2, 4, 3, 3};
+
+template <int R, typename T, bool GATE, int TY, int TXW>
+hipError_t launch_stream(const T* in, T* out, Geom g, uint32_t gate, int zs, hipStream_t s)
 {
-    const Variant v = kVariants[variant];
-    const int tiles_x = (g.nx + v.tx - 1) / v.tx, tiles_y = (g.ny + v.ty - 1) / v.ty;
-    if (zs <= 0) zs = default_zs(tiles_x * tiles_y, g.nz, v.target_groups);
+    constexpr int threads = M9Shape<R, TY, TXW>::THREADS;
+    const auto kern = mean9_stream<R, TY, T, GATE, TXW>;
+    const int tiles_x = (g.nx + TXW - 1) / TXW, tiles_y = (g.ny + TY - 1) / TY;
+    // default z-strip depth: one full round of resident workgroups
+    if (zs <= 0)
+        zs = default_zs(tiles_x * tiles_y, g.nz, resident_groups((const void*)kern, threads));
     const int nzs = (g.nz + zs - 1) / zs;
     const int total = tiles_x * tiles_y * nzs;
     const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
-    const double inv9n = 1.0 / (9.0 * n);
-    const T* pin = static_cast<const T*>(in);
-    T* pout = static_cast<T*>(out);
-    switch (variant) {
-    case 0:
-        hipLaunchKernelGGL((mean9_ring_64x16<R, T, GATE>), dim3(total), dim3(v.threads), 0, s,
-                           pin, pout, g, zs, tiles_x, tiles_y, total, gate, inv9n);
-        break;
-    case 1:
-        hipLaunchKernelGGL((mean9_stream<R, 16, T, GATE, 64, NARROW>), dim3(total),
-                           dim3(v.threads), 0, s, pin, pout, g, zs, tiles_x, tiles_y, total, gate,
-                           inv9n);
-        break;
-    case 2:
-        hipLaunchKernelGGL((mean9_stream<R, 32, T, GATE, 64, NARROW>), dim3(total),
-                           dim3(v.threads), 0, s, pin, pout, g, zs, tiles_x, tiles_y, total, gate,
-                           inv9n);
-        break;
-    case 3:
-        hipLaunchKernelGGL((mean9_stream<R, 16, T, GATE, 32, NARROW>), dim3(total),
-                           dim3(v.threads), 0, s, pin, pout, g, zs, tiles_x, tiles_y, total, gate,
-                           inv9n);
-        break;
-    default:
-        hipLaunchKernelGGL((mean9_stream<R, 32, T, GATE, 32, NARROW>), dim3(total),
-                           dim3(v.threads), 0, s, pin, pout, g, zs, tiles_x, tiles_y, total, gate,
-                           inv9n);
-        break;
-    }
+    hipLaunchKernelGGL(kern, dim3(total), dim3(threads), 0, s, in, out, g, zs, tiles_x, tiles_y,
+                       total, gate, 1.0 / (9.0 * n));
     return hipGetLastError();
 }
 
-template <int R, typename T, bool NARROW>
+template <int R, typename T, bool GATE>
+hipError_t launch_variant(int variant, const void* in, void* out, Geom g, uint32_t gate, int zs,
+                          hipStream_t s)
+{
+    const T* pin = static_cast<const T*>(in);
+    T* pout = static_cast<T*>(out);
+    switch (variant) {
+    case 0: {
+        const int tiles_x = (g.nx + 63) / 64, tiles_y = (g.ny + 15) / 16;
+        if (zs <= 0) zs = default_zs(tiles_x * tiles_y, g.nz, 1024);
+        const int total = tiles_x * tiles_y * ((g.nz + zs - 1) / zs);
+        const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
+        hipLaunchKernelGGL((mean9_ring_64x16<R, T, GATE>), dim3(total), dim3(kThreads), 0, s, pin,
+                           pout, g, zs, tiles_x, tiles_y, total, gate, 1.0 / (9.0 * n));
+        return hipGetLastError();
+    }
+    case 1: return launch_stream<R, T, GATE, 16, 64>(pin, pout, g, gate, zs, s);
+    case 2: return launch_stream<R, T, GATE, 32, 64>(pin, pout, g, gate, zs, s);
+    case 3: return launch_stream<R, T, GATE, 16, 32>(pin, pout, g, gate, zs, s);
+    default: return launch_stream<R, T, GATE, 32, 32>(pin, pout, g, gate, zs, s);
+    }
+}
+
+template <int R, typename T>
 hipError_t launch_r(int variant, const void* in, void* out, Geom g, uint32_t gate, int zs,
                     hipStream_t s)
 {
-    if (gate) return launch_variant<R, T, true, NARROW>(variant, in, out, g, gate, zs, s);
-    return launch_variant<R, T, false, NARROW>(variant, in, out, g, gate, zs, s);
+    if (gate) return launch_variant<R, T, true>(variant, in, out, g, gate, zs, s);
+    return launch_variant<R, T, false>(variant, in, out, g, gate, zs, s);
 }
 
-template <typename T, bool NARROW>
+template <typename T>
 hipError_t dispatch_r(const void* in, void* out, int r, Geom g, uint32_t gate, TileCfg cfg,
                       hipStream_t s)
 {
-    const int v = (cfg.variant >= 0 && cfg.variant < kNumVariants) ? cfg.variant : kDefaultVariant;
+    if (r < 1 || r > LNF_RADIUS_MAX) return hipErrorInvalidValue;
+    const int v = (cfg.variant >= 0 && cfg.variant < kNumVariants)
+                      ? cfg.variant
+                      : mean9_default_variant(sizeof(T) == 1 ? LNF_U8 : LNF_U16, r);
     switch (r) {
-    case 1: return launch_r<1, T, NARROW>(v, in, out, g, gate, cfg.zs, s);
-    case 2: return launch_r<2, T, NARROW>(v, in, out, g, gate, cfg.zs, s);
-    case 3: return launch_r<3, T, NARROW>(v, in, out, g, gate, cfg.zs, s);
-    case 4:
-        if constexpr (NARROW && sizeof(T) == 2) return hipErrorInvalidValue;  // 12-bit: r <= 3
-        else return launch_r<4, T, NARROW>(v, in, out, g, gate, cfg.zs, s);
-    default: return hipErrorInvalidValue;
+    case 1: return launch_r<1, T>(v, in, out, g, gate, cfg.zs, s);
+    case 2: return launch_r<2, T>(v, in, out, g, gate, cfg.zs, s);
+    case 3: return launch_r<3, T>(v, in, out, g, gate, cfg.zs, s);
+    default: return launch_r<4, T>(v, in, out, g, gate, cfg.zs, s);
     }
 }
 
 }  // namespace
 
 int mean9_variants() { return kNumVariants; }
-int mean9_default_variant() { return kDefaultVariant; }
+
+int mean9_default_variant(int dtype, int r)
+{
+    r = r < 1 ? 1 : r > LNF_RADIUS_MAX ? LNF_RADIUS_MAX : r;
+    return dtype == LNF_U8 ? kDefaultU8[r - 1] : kDefaultU16[r - 1];
+}
 
 void mean9_tile_shape(int variant, int* tx, int* ty)
 {
-    const Variant v = kVariants[(variant >= 0 && variant < kNumVariants) ? variant : kDefaultVariant];
+    const Variant v = kVariants[(variant >= 0 && variant < kNumVariants) ? variant : 1];
     *tx = v.tx;
     *ty = v.ty;
 }
 
 hipError_t launch_mean9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
-                        TileCfg cfg, hipStream_t s, bool narrow)
+                        TileCfg cfg, hipStream_t s)
 {
-    // uint8 data always fits the narrow path (x-pass sums <= 18 * 255)
-    if (dtype == LNF_U8) return dispatch_r<uint8_t, true>(in, out, r, g, gate, cfg, s);
-    if (narrow && r <= 3) return dispatch_r<uint16_t, true>(in, out, r, g, gate, cfg, s);
-    return dispatch_r<uint16_t, false>(in, out, r, g, gate, cfg, s);
+    if (dtype == LNF_U8) return dispatch_r<uint8_t>(in, out, r, g, gate, cfg, s);
+    return dispatch_r<uint16_t>(in, out, r, g, gate, cfg, s);
 }
 
 }  // namespace lnf

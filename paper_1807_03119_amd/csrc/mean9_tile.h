@@ -7,21 +7,23 @@
 // and c = ones on [-2r, 2r] plus one more at the centre (the two diagonal
 // clusters of an axis overlap there).  Everything is exact uint32.
 //
-// Pipeline per input slice k (one barrier per slice; stages listed in the
-// order they are issued within one iteration):
-//   - LDS DMA: the raw (TX+4r) x (TY+4r) tile of slice k+PF is loaded straight
-//     from HBM into LDS (one element per lane, zero-extended to 32 bits), its
-//     coordinates clamped into the volume per lane; PF+1 raw buffers form a
-//     ring, so each slice has PF iterations to arrive;
-//   - x-pass of slice k: each thread takes an 8-wide row segment, forms prefix
-//     sums over its 8+4r raw values and writes px = box_x E and qx = c_x E;
+// Pipeline per input slice k, in issue order within one iteration (one
+// barrier per iteration):
+//   - stores of the output slice finished in the previous iteration;
+//   - LDS reads of everything the iteration consumes: this thread's raw row
+//     segment of slice k and its px / qx column of slice k-1;
 //   - y-pass of slice k-1: each thread owns one column and four rows, forms
 //     P = box_y px and Q = c_y qx from prefix sums, and pushes them into a
 //     register ring of the last 4r+2 slices; the ring keeps the running sums
 //     B = sum of P over [z-r, z+r] and W = sum of Q over [z-2r, z+2r] for the
 //     output slice z, two r behind the newest slice, and S = B + W + Q(z);
-//   - out = round(S / 9n) (fp64, exact), gate, store (issued at the top of
-//     the next iteration).
+//     out = round(S / 9n) (fp64, exact), gate;
+//   - LDS DMA: the raw (TX+4r) x (TY+4r) tile of slice k+PF is loaded straight
+//     from HBM into LDS (one element per lane, zero-extended to 32 bits), its
+//     coordinates clamped into the volume per lane; PF+1 raw buffers form a
+//     ring, so each slice has PF iterations to arrive;
+//   - x-pass of slice k: each thread takes an 8-wide row segment, forms prefix
+//     sums over its 8+4r raw values and writes px = box_x E and qx = c_x E.
 // px and qx are double-buffered, so the x-pass of slice k overlaps the y-pass
 // of slice k-1.  Every iteration issues exactly NLOAD loads and YO stores (no
 // branch around any of them: masked-off stores go to an offset the buffer's
@@ -33,15 +35,6 @@
 #include "lnf_internal.h"
 
 namespace lnf {
-
-using u16x2 = unsigned short __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ u16x2 pack16(uint32_t lo, uint32_t hi)
-{
-    return __builtin_bit_cast(u16x2, (lo & 0xffffu) | (hi << 16));
-}
-
-__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 
 #ifndef LNF_M9_PREFETCH
 #define LNF_M9_PREFETCH 2
@@ -65,8 +58,7 @@ struct M9Shape {
     static constexpr int PXP = TX + 4;              // padded px/qx row pitch (words)
     static constexpr int D = 4 * R + 2;             // ring period (even)
     static constexpr int SEG = 8, NSEG = TX / SEG, SW = SEG + 4 * R;
-    static constexpr int XRW = (LY + 7) / 8 * 8;        // x-pass row slots, wide path
-    static constexpr int XRN = (LY / 2 + 7) / 8 * 8;    // x-pass row-pair slots, narrow path
+    static constexpr int XR = (LY + 7) / 8 * 8;     // x-pass row slots (multiple of 8)
     static constexpr int NPV = YO + 2 * R, NQV = YO + 4 * R;
     static constexpr int PF = LNF_M9_PREFETCH;       // slices staged ahead of the x-pass
     static constexpr int NRB = PF + 1;               // raw slice buffers (a ring)
@@ -74,7 +66,7 @@ struct M9Shape {
     // that needs that slice: PF-1 iterations of (NLOAD loads + YO stores)
     static constexpr int VMWAIT = (PF - 1) * (NLOAD + YO);
     static_assert(PF >= 1 && VMWAIT <= 63, "prefetch depth out of range");
-    static_assert(XRW * NSEG <= THREADS, "x-pass: one thread per row segment");
+    static_assert(XR * NSEG <= THREADS, "x-pass: one thread per row segment");
     static_assert(D % 2 == 0, "buffer parity must be static in the unrolled ring");
     static_assert(LX % 4 == 0, "x-pass reads 16-byte aligned rows");
 };
@@ -87,11 +79,7 @@ struct M9Smem {
     uint32_t qx[2][S::LY * S::PXP];
 };
 
-// NARROW: every x-pass sum fits 16 bits (values <= 65535 / (4r+2)); the x-pass
-// then runs on row pairs packed in 16-bit halves and stores px / qx as row
-// pairs, halving their LDS traffic.  Packed prefix sums wrap modulo 2^16, which
-// leaves every window difference exact because each window sum is < 2^16.
-template <int R, int TY, typename T, bool GATE, int TXW = 64, bool NARROW = false>
+template <int R, int TY, typename T, bool GATE, int TXW = 64>
 __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __restrict__ in,
                                            T* __restrict__ out, Geom g, int x0, int y0, int z0,
                                            int z1, uint32_t gate, double inv9n)
@@ -127,62 +115,31 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
     // (bank-conflict free with the padded pitch).  Row slots are padded to a
     // multiple of 8; surplus lanes and threads redo the last row or segment and
     // write the same values, so the x-pass needs no divergent branch.
-    constexpr int XR = NARROW ? S::XRN : S::XRW;
-    const int xrow = min(tid % XR, (NARROW ? S::LY / 2 : S::LY) - 1);
-    const int xseg = min(tid / XR, S::NSEG - 1);
-    auto xpass = [&](int buf, int slot) {
-        if constexpr (NARROW) {
-            // rows 2*xrow and 2*xrow+1, packed as (low, high) 16-bit halves
-            u16x2 wp[S::SW], c[S::SW];
-            const uint32_t* r0 = sm.raw[slot] + (2 * xrow) * LX + xseg * S::SEG;
-            const uint32_t* r1 = r0 + LX;
-#pragma unroll
-            for (int i = 0; i < S::SW; i += 4) {
-                const uint4 a = *reinterpret_cast<const uint4*>(r0 + i);
-                const uint4 b = *reinterpret_cast<const uint4*>(r1 + i);
-                wp[i] = pack16(a.x, b.x);
-                wp[i + 1] = pack16(a.y, b.y);
-                wp[i + 2] = pack16(a.z, b.z);
-                wp[i + 3] = pack16(a.w, b.w);
-            }
-            c[0] = wp[0];
-#pragma unroll
-            for (int i = 1; i < S::SW; ++i) c[i] = c[i - 1] + wp[i];
-            uint32_t pp[S::SEG], qq[S::SEG];
-#pragma unroll
-            for (int m = 0; m < S::SEG; ++m) {
-                const u16x2 zero = {0, 0};
-                qq[m] = as_u32(c[m + 4 * R] - (m ? c[m - 1] : zero) + wp[m + 2 * R]);
-                pp[m] = as_u32(c[m + 3 * R] - c[m + R - 1]);
-            }
-            uint32_t* pd = sm.px[buf] + xrow * PXP + xseg * S::SEG;
-            uint32_t* qd = sm.qx[buf] + xrow * PXP + xseg * S::SEG;
-#pragma unroll
-            for (int m = 0; m < S::SEG; m += 4) {
-                *reinterpret_cast<uint4*>(pd + m) =
-                    make_uint4(pp[m], pp[m + 1], pp[m + 2], pp[m + 3]);
-                *reinterpret_cast<uint4*>(qd + m) =
-                    make_uint4(qq[m], qq[m + 1], qq[m + 2], qq[m + 3]);
-            }
-            return;
-        }
-        uint32_t w[S::SW], c[S::SW];
+    const int xrow = min(tid % S::XR, S::LY - 1);
+    const int xseg = min(tid / S::XR, S::NSEG - 1);
+    // x-pass, part 1: this thread's raw row segment, read from LDS at the top
+    // of the iteration so the reads overlap the y-pass
+    uint32_t xw[S::SW];
+    auto xload = [&](int slot) {
         const uint32_t* rp = sm.raw[slot] + xrow * LX + xseg * S::SEG;
 #pragma unroll
         for (int i = 0; i < S::SW; i += 4) {
             const uint4 t4 = *reinterpret_cast<const uint4*>(rp + i);
-            w[i] = t4.x;
-            w[i + 1] = t4.y;
-            w[i + 2] = t4.z;
-            w[i + 3] = t4.w;
+            xw[i] = t4.x;
+            xw[i + 1] = t4.y;
+            xw[i + 2] = t4.z;
+            xw[i + 3] = t4.w;
         }
-        c[0] = w[0];
+    };
+    // x-pass, part 2: prefix sums over the segment, px and qx written to LDS
+    auto xpass = [&](int buf) {
+        uint32_t pp[S::SEG], qq[S::SEG], c[S::SW];
+        c[0] = xw[0];
 #pragma unroll
-        for (int i = 1; i < S::SW; ++i) c[i] = c[i - 1] + w[i];
-        uint32_t pp[S::SEG], qq[S::SEG];
+        for (int i = 1; i < S::SW; ++i) c[i] = c[i - 1] + xw[i];
 #pragma unroll
         for (int m = 0; m < S::SEG; ++m) {
-            qq[m] = c[m + 4 * R] - (m ? c[m - 1] : 0u) + w[m + 2 * R];
+            qq[m] = c[m + 4 * R] - (m ? c[m - 1] : 0u) + xw[m + 2 * R];
             pp[m] = c[m + 3 * R] - c[m + R - 1];
         }
         uint32_t* pd = sm.px[buf] + xrow * PXP + xseg * S::SEG;
@@ -196,13 +153,7 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
 
     // Value of px (Q = false) or qx (Q = true) at x-pass row `row`, column xq.
     auto xval = [&](int pb, bool q, int row) -> uint32_t {
-        const uint32_t* a = q ? sm.qx[pb] : sm.px[pb];
-        if constexpr (NARROW) {
-            const uint32_t w = a[(row >> 1) * PXP + xq];
-            return (row & 1) ? (w >> 16) : (w & 0xffffu);
-        } else {
-            return a[row * PXP + xq];
-        }
+        return (q ? sm.qx[pb] : sm.px[pb])[row * PXP + xq];
     };
 
     // y-pass / ring ownership: column xq, rows yg*YO .. yg*YO+YO-1
@@ -264,6 +215,7 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
             const int k = kb + u;  // x-pass of slice k, y-pass of slice k-1
             if (k > ns) break;
             flush();
+            xload(k % S::NRB);
             const int buf = u & 1;  // == k & 1 because D is even
             const int pb = buf ^ 1;
             uint32_t cp[S::NPV], cq[S::NQV], qc[YO];
@@ -298,7 +250,7 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
             // slice i lives in raw slot i mod NRB: slice k+PF takes the slot
             // slice k-1 used, read in the previous iteration
             stage(z0 - H + k + S::PF, (k + S::PF) % S::NRB);
-            xpass(buf, k % S::NRB);
+            xpass(buf);
             wait_vmem_le<S::VMWAIT>();  // slice k+1 has landed
             barrier_lds();
         }

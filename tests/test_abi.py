@@ -62,8 +62,9 @@ def test_create_bad_options():
     assert lib.lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
     opt = _lib.lnf_options(4, 0, 0, -1, 0)
     assert lib.lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
-    opt = _lib.lnf_options(ctypes.sizeof(_lib.lnf_options), 0, 0, -1, 2)  # unknown flag bit
-    assert lib.lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
+    for flags in (1, 2):  # reserved: must be 0
+        opt = _lib.lnf_options(ctypes.sizeof(_lib.lnf_options), 0, 0, -1, flags)
+        assert lib.lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
 
 
 def test_create_without_gpu_reports_device_error():

@@ -132,11 +132,14 @@ def test_tune_keeps_results_and_cache_roundtrip(rule):
             assert _lib.lnf_tune_load(f.handle, os.path.join(d, "missing")) == _lib.LNF_EINVAL
 
 
-def test_batch_declared_12bit():
+def test_batch_extreme_values_both_types():
+    """Extreme-valued uint16 and uint8 volumes of every radius in one batch."""
     from paper_1807_03119_amd.api import Filter
-    jobs = [(ph.ct_u12((50, 40, 30), seed=60 + r), r) for r in (1, 2, 3, 4)]
-    jobs += [(ph.small_u8(70 + r, dims=(33, 20, 17)), r) for r in (1, 4)]
-    with Filter(_lib.LNF_MEAN9, 0, flags=_lib.LNF_FLAG_DATA_12BIT) as f:
+    jobs = [(ph.random_volume((50, 40, 30), np.uint16, seed=60 + r, kind="extreme"), r)
+            for r in (1, 2, 3, 4)]
+    jobs += [(ph.random_volume((33, 20, 17), np.uint8, seed=70 + r, kind="extreme"), r)
+             for r in (1, 4)]
+    with Filter(_lib.LNF_MEAN9, 0) as f:
         outs = f.batch([(torch.from_numpy(v).cuda(), r) for v, r in jobs])
         for (v, r), o in zip(jobs, outs):
             np.testing.assert_array_equal(o.cpu().numpy(), oracle.filter_volume(v, r))

@@ -223,22 +223,23 @@ def test_error_codes(filters):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
-def test_declared_12bit_data_narrow_path(variant):
-    """With LNF_FLAG_DATA_12BIT the uint16 kernels keep x-pass sums in 16 bits
-    (r <= 3; r = 4 falls back to 32 bits); results stay bit-exact."""
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+def test_extreme_values_every_variant(variant):
+    """Voxels at the type's extremes (0 and the maximum) give the largest
+    cluster sums the kernels can see; bit-exact for both voxel types."""
     from paper_1807_03119_amd.api import Filter
-    vol = ph.ct_u12((130, 67, 45), seed=2500)
-    extreme = (ph.random_volume((70, 33, 20), np.uint16, seed=3, kind="extreme") // 65535) * 4095
-    with Filter(_lib.LNF_MEAN9, 0, flags=_lib.LNF_FLAG_DATA_12BIT) as f:
-        for v in (vol, extreme.astype(np.uint16)):
+    u16 = ph.random_volume((70, 33, 20), np.uint16, seed=3, kind="extreme")
+    u8 = ph.random_volume((45, 38, 21), np.uint8, seed=4, kind="extreme")
+    with Filter(_lib.LNF_MEAN9, 0) as f:
+        for v in (u16, u8):
             for r in (1, 2, 3, 4):
                 got = _gpu(f, v, r, variant=variant)
-                _assert_same(got, oracle.filter_volume(v, r), v, r, f"12-bit v{variant} r={r}")
+                _assert_same(got, oracle.filter_volume(v, r), v, r, f"extremes v{variant} r={r}")
 
 
-def test_unknown_flags_rejected():
+def test_reserved_flags_rejected():
     import ctypes
     h = ctypes.c_void_p()
-    opt = _lib.lnf_options(ctypes.sizeof(_lib.lnf_options), 0, 0, -1, 2)
-    assert _lib.lib().lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
+    for flags in (1, 2, 0x80000000):
+        opt = _lib.lnf_options(ctypes.sizeof(_lib.lnf_options), 0, 0, -1, flags)
+        assert _lib.lib().lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
