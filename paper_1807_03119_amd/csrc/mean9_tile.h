@@ -87,7 +87,8 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
     using S = M9Shape<R, TY, TXW>;
     constexpr int H = S::H, LX = S::LX, D = S::D, TX = S::TX, PXP = S::PXP, YO = S::YO;
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    // wave index as a scalar, so the LDS DMA destinations are scalar arithmetic
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const size_t plane = (size_t)g.nx * g.ny;
     const uint32_t pbytes = (uint32_t)(plane * sizeof(T));
 
@@ -178,75 +179,81 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
 
     // The y-pass of the first iteration reads px/qx buffer 1 before any x-pass
     // wrote it; zeros there push zeros into the (zero) ring, so the loop body
-    // needs no branch around the y-pass.  Likewise the x-pass and the staging
-    // run in every iteration (the extra ones at the end read clamped slices and
-    // their results are never used).  The loop body is then one basic block the
-    // compiler can interleave; only the stores are conditional, and they are
-    // issued at the top of the next iteration so their latency overlaps work.
+    // needs no branch.  Likewise the x-pass and the staging run
+    // in every iteration (the extra ones at the end read clamped slices and
+    // their results are never used).  The loop body is then one basic block
+    // the compiler can interleave.
     for (int i = tid; i < S::LY * PXP; i += S::THREADS) {
         sm.px[1][i] = 0;
         sm.qx[1][i] = 0;
     }
     const int ns = (z1 - z0) + 2 * H;  // input slices z0-2r .. z1-1+2r
-    uint32_t opend[YO];
-#pragma unroll
-    for (int m = 0; m < YO; ++m) opend[m] = 0;
-    int zpend = -1;  // output slice whose values wait in opend, or -1
-    // stores of opend; with no pending slice they go to an empty buffer
+    // the YO stores of output slice zo; zo < 0 stores to an empty buffer
     // resource (every access dropped), so each call issues exactly YO stores
-    auto flush = [&]() {
-        const rsrc_t wr = make_rsrc(out + (size_t)max(zpend, 0) * plane, zpend >= 0 ? pbytes : 0u);
+    auto store_out = [&](int zo, const uint32_t(&o)[YO]) {
+        const rsrc_t wr = make_rsrc(out + (size_t)max(zo, 0) * plane, zo >= 0 ? pbytes : 0u);
 #pragma unroll
-        for (int m = 0; m < YO; ++m) buffer_store<T>(opend[m], wr, soff[m], 0u);
+        for (int m = 0; m < YO; ++m) buffer_store<T>(o[m], wr, soff[m], 0u);
     };
     // prologue: slices 0 .. PF-1, each but the first preceded by YO (dropped)
     // stores so the operation pattern matches the loop's
     stage(z0 - H, 0);
 #pragma unroll
     for (int p = 1; p < S::PF; ++p) {
-        flush();
+        store_out(-1, bacc);
         stage(z0 - H + p, p);
     }
     wait_vmem_le<S::VMWAIT>();
     barrier_lds();
-    for (int kb = 0; kb <= ns; kb += D) {
+    // iteration k: x-pass of slice k, y-pass of slice k-1, z-window and output
+    // of slice k-2 (the z-window work needs no LDS data, so it runs while the
+    // iteration's LDS reads are in flight)
+    const int nk = ns + 1;
+    for (int kb = 0; kb <= nk; kb += D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) {
-            const int k = kb + u;  // x-pass of slice k, y-pass of slice k-1
-            if (k > ns) break;
-            flush();
+            const int k = kb + u;
+            if (k > nk) break;
             xload(k % S::NRB);
             const int buf = u & 1;  // == k & 1 because D is even
             const int pb = buf ^ 1;
-            uint32_t cp[S::NPV], cq[S::NQV], qc[YO];
-            cp[0] = xval(pb, false, yg * YO + R);
+            uint32_t pv[S::NPV], qv[S::NQV];
 #pragma unroll
-            for (int i = 1; i < S::NPV; ++i) cp[i] = cp[i - 1] + xval(pb, false, yg * YO + R + i);
+            for (int i = 0; i < S::NPV; ++i) pv[i] = xval(pb, false, yg * YO + R + i);
+#pragma unroll
+            for (int i = 0; i < S::NQV; ++i) qv[i] = xval(pb, true, yg * YO + i);
             {
-                uint32_t qv[S::NQV];
+                // z-window of slice j = k-2, whose P and Q entered the ring in
+                // the previous iteration; it reads slot j+1 (Q of slice j-4r-1)
+                // before the y-pass below overwrites it with slice k-1
+                const int uj = (u + D - 2) % D;
+                uint32_t o[YO];
 #pragma unroll
-                for (int i = 0; i < S::NQV; ++i) qv[i] = xval(pb, true, yg * YO + i);
+                for (int m = 0; m < YO; ++m) {
+                    bacc[m] += pr[(uj + D - R) % D][m] - pr[(uj + R + 1) % D][m];
+                    wacc[m] += qr[uj][m] - qr[(uj + 1) % D][m];
+                    const uint32_t Ssum = bacc[m] + wacc[m] + qr[(uj + D - 2 * R) % D][m];
+                    o[m] = round_div_odd(Ssum, inv9n);
+                    if (GATE && o[m] < gate) o[m] = 0;
+                }
+                store_out((k - 2 >= 2 * H) ? z0 + k - 2 - 2 * H : -1, o);
+            }
+            {
+                // y-pass of slice k-1 into ring slot k-1
+                const int uy = (u + D - 1) % D;
+                uint32_t cp[S::NPV], cq[S::NQV];
+                cp[0] = pv[0];
                 cq[0] = qv[0];
+#pragma unroll
+                for (int i = 1; i < S::NPV; ++i) cp[i] = cp[i - 1] + pv[i];
 #pragma unroll
                 for (int i = 1; i < S::NQV; ++i) cq[i] = cq[i - 1] + qv[i];
 #pragma unroll
-                for (int m = 0; m < YO; ++m) qc[m] = qv[m + 2 * R];
+                for (int m = 0; m < YO; ++m) {
+                    pr[uy][m] = cp[m + 2 * R] - (m ? cp[m - 1] : 0u);
+                    qr[uy][m] = cq[m + 4 * R] - (m ? cq[m - 1] : 0u) + qv[m + 2 * R];
+                }
             }
-            const int uj = (u + D - 1) % D;  // ring slot of slice j = k-1
-#pragma unroll
-            for (int m = 0; m < YO; ++m) {
-                const uint32_t P = cp[m + 2 * R] - (m ? cp[m - 1] : 0u);
-                const uint32_t Q = cq[m + 4 * R] - (m ? cq[m - 1] : 0u) + qc[m];
-                bacc[m] += pr[(uj + D - R) % D][m] - pr[(uj + R + 1) % D][m];
-                wacc[m] += Q - qr[(uj + 1) % D][m];
-                pr[uj][m] = P;
-                qr[uj][m] = Q;
-                const uint32_t Ssum = bacc[m] + wacc[m] + qr[(uj + D - 2 * R) % D][m];
-                uint32_t o = round_div_odd(Ssum, inv9n);
-                if (GATE && o < gate) o = 0;
-                opend[m] = o;
-            }
-            zpend = (k - 1 >= 2 * H) ? z0 + k - 1 - 2 * H : -1;
             // slice i lives in raw slot i mod NRB: slice k+PF takes the slot
             // slice k-1 used, read in the previous iteration
             stage(z0 - H + k + S::PF, (k + S::PF) % S::NRB);
@@ -255,7 +262,6 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
             barrier_lds();
         }
     }
-    flush();
     // drain the staging of the slices past the end before the LDS is reused
     wait_vmem();
     barrier_lds();
