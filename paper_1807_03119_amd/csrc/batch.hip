@@ -33,6 +33,7 @@ struct BatchJobDesc {
     void* out;
     int nx, ny, nz, dtype;
     int tiles_x, tiles_y, zs, tile_begin;  // tile_begin: first tile in its class queue
+    int pairs;                             // MEAN9 stages element pairs (mean9_pairs_ok)
 };
 
 struct BatchQueue {
@@ -83,7 +84,7 @@ template <int R, bool GATE>
 __global__ __launch_bounds__((M9Shape<R, kMean9TY>::THREADS)) void mean9_batch(BatchTable* tab,
                                                                              uint32_t gate)
 {
-    __shared__ __align__(16) M9Smem<R, kMean9TY> sm;
+    __shared__ __align__(16) M9SmemAny<R, kMean9TY> sm;
     __shared__ int s_tile, s_job;
     constexpr int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
     const double inv9n = 1.0 / (9.0 * n);
@@ -98,12 +99,14 @@ __global__ __launch_bounds__((M9Shape<R, kMean9TY>::THREADS)) void mean9_batch(B
         const int bz = rest / d.tiles_y;
         const Geom g{d.nx, d.ny, d.nz};
         const int z0 = bz * d.zs, z1 = min(z0 + d.zs, d.nz);
+        const int x0 = bx * 64, y0 = by * kMean9TY;
         if (d.dtype == LNF_U8)
-            mean9_tile<R, kMean9TY, uint8_t, GATE>(sm, (const uint8_t*)d.in, (uint8_t*)d.out, g,
-                                                   bx * 64, by * kMean9TY, z0, z1, gate, inv9n);
+            mean9_tile<R, kMean9TY, uint8_t, GATE>(sm, d.pairs != 0, (const uint8_t*)d.in,
+                                                   (uint8_t*)d.out, g, x0, y0, z0, z1, gate,
+                                                   inv9n);
         else
-            mean9_tile<R, kMean9TY, uint16_t, GATE>(sm, (const uint16_t*)d.in, (uint16_t*)d.out,
-                                                    g, bx * 64, by * kMean9TY, z0, z1, gate,
+            mean9_tile<R, kMean9TY, uint16_t, GATE>(sm, d.pairs != 0, (const uint16_t*)d.in,
+                                                    (uint16_t*)d.out, g, x0, y0, z0, z1, gate,
                                                     inv9n);
     }
 }
@@ -349,6 +352,7 @@ int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>
         d.ny = g.ny;
         d.nz = g.nz;
         d.dtype = jobs[i].dtype;
+        d.pairs = mean9_pairs_ok(d.in, g.nx, jobs[i].dtype == LNF_U8 ? 1 : 2) ? 1 : 0;
         const TileCfg cfg = ctx_tile(h, h->rule, jobs[i].dtype, jobs[i].radius, g);
         d.zs = cfg.zs > 0 ? std::min(cfg.zs, g.nz) : batch_default_zs(g.nz);
         d.tiles_x = (g.nx + tx - 1) / tx;

@@ -78,6 +78,24 @@ __device__ __forceinline__ void buffer_load_lds<uint16_t>(rsrc_t r, void* dst_wa
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)dst_wave, 2, voff, 0, 0, 0);
 }
 
+// LDS DMA of two adjacent elements per lane (the byte offset must be a multiple
+// of 2 * sizeof(T)): a uint16 pair fills the 32-bit LDS word, a uint8 pair
+// lands zero-extended in its low 16 bits.
+template <typename T>
+__device__ __forceinline__ void buffer_load_lds_pair(rsrc_t r, void* dst_wave, uint32_t voff);
+template <>
+__device__ __forceinline__ void buffer_load_lds_pair<uint8_t>(rsrc_t r, void* dst_wave,
+                                                              uint32_t voff)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)dst_wave, 2, voff, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ void buffer_load_lds_pair<uint16_t>(rsrc_t r, void* dst_wave,
+                                                               uint32_t voff)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)dst_wave, 4, voff, 0, 0, 0);
+}
+
 // Wait for this wave's outstanding vector-memory operations (including LDS DMA).
 __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 

@@ -30,6 +30,12 @@ int mean9_default_variant(int dtype, int r);
 void mean9_tile_shape(int variant, int* tx, int* ty);
 hipError_t launch_mean9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
                         TileCfg cfg, hipStream_t s);
+// Whether a volume can be staged as element pairs: even row length and a base
+// address aligned to a pair of elements.
+inline bool mean9_pairs_ok(const void* base, int nx, size_t elem)
+{
+    return nx % 2 == 0 && reinterpret_cast<uintptr_t>(base) % (2 * elem) == 0;
+}
 
 // ---- MINVAR9 (least-variance cluster) -------------------------------------
 int minvar9_variants();

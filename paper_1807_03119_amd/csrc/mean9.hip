@@ -185,20 +185,20 @@ __global__ __launch_bounds__(kThreads) void mean9_ring_64x16(const T* __restrict
 }
 
 // Single-volume wrapper around the streaming tile body of mean9_tile.h.
-template <int R, int TY, typename T, bool GATE, int TXW = 64>
+template <int R, int TY, typename T, bool GATE, int TXW>
 __global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS)) void mean9_stream(
     const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
-    int total, uint32_t gate, double inv9n)
+    int total, uint32_t gate, double inv9n, int pairs)
 {
-    __shared__ __align__(16) M9Smem<R, TY, TXW> sm;
+    __shared__ __align__(16) M9SmemAny<R, TY, TXW> sm;
     const int tile = xcd_tile(blockIdx.x, total);
     const int bx = tile % tiles_x;
     const int rest = tile / tiles_x;
     const int by = rest % tiles_y;
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
-    mean9_tile<R, TY, T, GATE, TXW>(sm, in, out, g, bx * TXW, by * TY, z0, min(z0 + zs, g.nz),
-                                    gate, inv9n);
+    mean9_tile<R, TY, T, GATE, TXW>(sm, pairs != 0, in, out, g, bx * TXW, by * TY, z0,
+                                    min(z0 + zs, g.nz), gate, inv9n);
 }
 
 struct Variant {
@@ -218,6 +218,7 @@ constexpr int kDefaultU8[LNF_RADIUS_MAX] = {2, 4, 3, 3};
 template <int R, typename T, bool GATE, int TY, int TXW>
 hipError_t launch_stream(const T* in, T* out, Geom g, uint32_t gate, int zs, hipStream_t s)
 {
+    static_assert(M9Shape<R, TY, TXW, true>::THREADS == M9Shape<R, TY, TXW>::THREADS, "");
     constexpr int threads = M9Shape<R, TY, TXW>::THREADS;
     const auto kern = mean9_stream<R, TY, T, GATE, TXW>;
     const int tiles_x = (g.nx + TXW - 1) / TXW, tiles_y = (g.ny + TY - 1) / TY;
@@ -227,8 +228,9 @@ hipError_t launch_stream(const T* in, T* out, Geom g, uint32_t gate, int zs, hip
     const int nzs = (g.nz + zs - 1) / zs;
     const int total = tiles_x * tiles_y * nzs;
     const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
+    const int pairs = mean9_pairs_ok(in, g.nx, sizeof(T)) ? 1 : 0;
     hipLaunchKernelGGL(kern, dim3(total), dim3(threads), 0, s, in, out, g, zs, tiles_x, tiles_y,
-                       total, gate, 1.0 / (9.0 * n));
+                       total, gate, 1.0 / (9.0 * n), pairs);
     return hipGetLastError();
 }
 

@@ -40,24 +40,34 @@ namespace lnf {
 #define LNF_M9_PREFETCH 2
 #endif
 
-template <int R, int TY, int TXW = 64>
+// PK: the raw tile is staged as element pairs, one 32-bit LDS word per pair
+// (uint16: both halves; uint8: the low two bytes), loaded by one LDS DMA per
+// lane.  That halves the DMA instructions and the LDS bytes of the staging and
+// of the x-pass reads.  It needs an even nx (pairs never straddle a row end), a
+// volume base aligned to a pair, and a tile whose halo stays inside the volume
+// in x (a pair cannot be clamped element by element); tiles at an x face are
+// staged element-wise.
+template <int R, int TY, int TXW = 64, bool PK = false>
 struct M9Shape {
     static constexpr int TX = TXW;
     static constexpr int YO = 4;                    // output rows per thread
     static constexpr int THREADS = TX * TY / YO;    // one thread per column x YO rows
     static constexpr int H = 2 * R;                 // halo: cluster radius + offset
-    // Raw row pitch: the 4r-column halo plus padding to 4 mod 8 words, so that
-    // eight consecutive rows start in eight different groups of four LDS banks
-    // (the x-pass reads 16 bytes per lane, eight lanes per bank cycle).  The
-    // padding columns are loaded like halo (clamped) and never used.
-    static constexpr int LX = (TX + 4 * R) % 8 == 4 ? TX + 4 * R : TX + 4 * R + 4;
+    static constexpr int EPW = PK ? 2 : 1;          // raw elements per LDS word
+    static constexpr int LXE = TX + 4 * R;          // raw elements per tile row
+    static constexpr int LXW = LXE / EPW;           // LDS words holding them (LXE even)
+    // Raw row pitch in words: padded to 4 mod 8, so that eight consecutive
+    // rows start in eight different groups of four LDS banks (the x-pass reads
+    // 16 bytes per lane, eight lanes per bank cycle).  The padding words are
+    // loaded like halo (clamped) and never used.
+    static constexpr int LX = LXW + (12 - LXW % 8) % 8;
     static constexpr int LY = TY + 2 * H;
-    static constexpr int NRAW = LX * LY;
+    static constexpr int NRAW = LX * LY;            // staged words per slice
     static constexpr int NLOAD = (NRAW + THREADS - 1) / THREADS;
-    static constexpr int NFULL = NRAW / THREADS;
     static constexpr int PXP = TX + 4;              // padded px/qx row pitch (words)
     static constexpr int D = 4 * R + 2;             // ring period (even)
     static constexpr int SEG = 8, NSEG = TX / SEG, SW = SEG + 4 * R;
+    static constexpr int SWW = SW / EPW;            // words an x-pass segment reads
     static constexpr int XR = (LY + 7) / 8 * 8;     // x-pass row slots (multiple of 8)
     static constexpr int NPV = YO + 2 * R, NQV = YO + 4 * R;
     static constexpr int PF = LNF_M9_PREFETCH;       // slices staged ahead of the x-pass
@@ -68,47 +78,54 @@ struct M9Shape {
     static_assert(PF >= 1 && VMWAIT <= 63, "prefetch depth out of range");
     static_assert(XR * NSEG <= THREADS, "x-pass: one thread per row segment");
     static_assert(D % 2 == 0, "buffer parity must be static in the unrolled ring");
-    static_assert(LX % 4 == 0, "x-pass reads 16-byte aligned rows");
+    static_assert(LX % 4 == 0 && (SEG / EPW) % 4 == 0, "x-pass reads 16-byte aligned rows");
+    static_assert(SWW % 2 == 0 && LXE % 2 == 0, "x-pass reads whole 8-byte pieces");
 };
 
-template <int R, int TY, int TXW = 64>
+template <int R, int TY, int TXW = 64, bool PK = false>
 struct M9Smem {
-    using S = M9Shape<R, TY, TXW>;
+    using S = M9Shape<R, TY, TXW, PK>;
     uint32_t raw[S::NRB][S::NLOAD * S::THREADS];
     uint32_t px[2][S::LY * S::PXP];
     uint32_t qx[2][S::LY * S::PXP];
 };
 
-template <int R, int TY, typename T, bool GATE, int TXW = 64>
-__device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __restrict__ in,
-                                           T* __restrict__ out, Geom g, int x0, int y0, int z0,
-                                           int z1, uint32_t gate, double inv9n)
+template <int R, int TY, typename T, bool GATE, int TXW, bool PK>
+__device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK>& sm,
+                                                const T* __restrict__ in, T* __restrict__ out,
+                                                Geom g, int x0, int y0, int z0, int z1,
+                                                uint32_t gate, double inv9n)
 {
-    using S = M9Shape<R, TY, TXW>;
+    using S = M9Shape<R, TY, TXW, PK>;
     constexpr int H = S::H, LX = S::LX, D = S::D, TX = S::TX, PXP = S::PXP, YO = S::YO;
+    constexpr int EPW = S::EPW;
     const int tid = threadIdx.x;
     // wave index as a scalar, so the LDS DMA destinations are scalar arithmetic
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const size_t plane = (size_t)g.nx * g.ny;
     const uint32_t pbytes = (uint32_t)(plane * sizeof(T));
 
-    // byte offsets (within a slice) of the raw elements this lane stages
+    // byte offsets (within a slice) of the raw words this lane stages
     uint32_t off[S::NLOAD];
 #pragma unroll
     for (int i = 0; i < S::NLOAD; ++i) {
         const int e = min(tid + i * S::THREADS, S::NRAW - 1);
         const int row = e / LX, col = e - row * LX;
         const int gy = clampi(y0 - H + row, 0, g.ny - 1);
-        const int gx = clampi(x0 - H + col, 0, g.nx - 1);
+        const int gx = clampi(x0 - H + EPW * col, 0, g.nx - EPW);  // even when PK
         off[i] = (uint32_t)(gy * g.nx + gx) * (uint32_t)sizeof(T);
     }
     // every lane issues all NLOAD loads (lanes past the tile reload its last
-    // element into unused LDS words), so the count per stage is fixed
+    // word into unused LDS words), so the count per stage is fixed
     auto stage = [&](int zi, int slot) {
         const rsrc_t rs = make_rsrc(in + (size_t)clampi(zi, 0, g.nz - 1) * plane, pbytes);
 #pragma unroll
-        for (int i = 0; i < S::NLOAD; ++i)
-            buffer_load_lds<T>(rs, &sm.raw[slot][i * S::THREADS + wave * 64], off[i]);
+        for (int i = 0; i < S::NLOAD; ++i) {
+            if constexpr (PK)
+                buffer_load_lds_pair<T>(rs, &sm.raw[slot][i * S::THREADS + wave * 64], off[i]);
+            else
+                buffer_load_lds<T>(rs, &sm.raw[slot][i * S::THREADS + wave * 64], off[i]);
+        }
     };
 
     const int xq = tid % TX;
@@ -118,29 +135,39 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
     // write the same values, so the x-pass needs no divergent branch.
     const int xrow = min(tid % S::XR, S::LY - 1);
     const int xseg = min(tid / S::XR, S::NSEG - 1);
+    auto half = [](uint32_t w, int h) -> uint32_t {
+        return h ? (w >> (8 * sizeof(T))) : (w & ((1u << (8 * sizeof(T))) - 1u));
+    };
     // x-pass, part 1: this thread's raw row segment, read from LDS at the top
     // of the iteration so the reads overlap the y-pass
-    uint32_t xw[S::SW];
+    uint32_t xw[S::SWW];
     auto xload = [&](int slot) {
-        const uint32_t* rp = sm.raw[slot] + xrow * LX + xseg * S::SEG;
+        const uint32_t* rp = sm.raw[slot] + xrow * LX + xseg * (S::SEG / EPW);
 #pragma unroll
-        for (int i = 0; i < S::SW; i += 4) {
-            const uint4 t4 = *reinterpret_cast<const uint4*>(rp + i);
-            xw[i] = t4.x;
-            xw[i + 1] = t4.y;
-            xw[i + 2] = t4.z;
-            xw[i + 3] = t4.w;
+        for (int i = 0; i < S::SWW; i += 4) {
+            if (i + 4 <= S::SWW) {
+                const uint4 t4 = *reinterpret_cast<const uint4*>(rp + i);
+                xw[i] = t4.x;
+                xw[i + 1] = t4.y;
+                xw[i + 2] = t4.z;
+                xw[i + 3] = t4.w;
+            } else {
+                const uint2 t2 = *reinterpret_cast<const uint2*>(rp + i);
+                xw[i] = t2.x;
+                xw[i + 1] = t2.y;
+            }
         }
     };
-    // x-pass, part 2: prefix sums over the segment, px and qx written to LDS
-    auto xpass = [&](int buf) {
+    // x-pass, part 2: prefix sums over the segment, px and qx written to LDS;
+    // el(i) is raw element i of the segment
+    auto xsums = [&](int buf, auto el) {
         uint32_t pp[S::SEG], qq[S::SEG], c[S::SW];
-        c[0] = xw[0];
+        c[0] = el(0);
 #pragma unroll
-        for (int i = 1; i < S::SW; ++i) c[i] = c[i - 1] + xw[i];
+        for (int i = 1; i < S::SW; ++i) c[i] = c[i - 1] + el(i);
 #pragma unroll
         for (int m = 0; m < S::SEG; ++m) {
-            qq[m] = c[m + 4 * R] - (m ? c[m - 1] : 0u) + xw[m + 2 * R];
+            qq[m] = c[m + 4 * R] - (m ? c[m - 1] : 0u) + el(m + 2 * R);
             pp[m] = c[m + 3 * R] - c[m + R - 1];
         }
         uint32_t* pd = sm.px[buf] + xrow * PXP + xseg * S::SEG;
@@ -149,6 +176,13 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
         for (int m = 0; m < S::SEG; m += 4) {
             *reinterpret_cast<uint4*>(pd + m) = make_uint4(pp[m], pp[m + 1], pp[m + 2], pp[m + 3]);
             *reinterpret_cast<uint4*>(qd + m) = make_uint4(qq[m], qq[m + 1], qq[m + 2], qq[m + 3]);
+        }
+    };
+    auto xpass = [&](int buf) {
+        if constexpr (PK) {
+            xsums(buf, [&](int i) -> uint32_t { return half(xw[i / 2], i & 1); });
+        } else {
+            xsums(buf, [&](int i) -> uint32_t { return xw[i]; });
         }
     };
 
@@ -265,6 +299,29 @@ __device__ __forceinline__ void mean9_tile(M9Smem<R, TY, TXW>& sm, const T* __re
     // drain the staging of the slices past the end before the LDS is reused
     wait_vmem();
     barrier_lds();
+}
+
+// LDS for either staging; a kernel that may run both holds the union.
+template <int R, int TY, int TXW = 64>
+union M9SmemAny {
+    M9Smem<R, TY, TXW, false> e;  // element-wise staging
+    M9Smem<R, TY, TXW, true> p;   // paired staging
+};
+
+// One tile; `pairs` (mean9_pairs_ok for the volume) selects paired staging
+// for the tiles whose x halo stays inside the volume.
+template <int R, int TY, typename T, bool GATE, int TXW = 64>
+__device__ __forceinline__ void mean9_tile(M9SmemAny<R, TY, TXW>& sm, bool pairs,
+                                           const T* __restrict__ in, T* __restrict__ out, Geom g,
+                                           int x0, int y0, int z0, int z1, uint32_t gate,
+                                           double inv9n)
+{
+    constexpr int H = 2 * R, LXE = TXW + 4 * R;
+    if (pairs && x0 - H >= 0 && x0 - H + LXE <= g.nx)
+        mean9_tile_body<R, TY, T, GATE, TXW, true>(sm.p, in, out, g, x0, y0, z0, z1, gate, inv9n);
+    else
+        mean9_tile_body<R, TY, T, GATE, TXW, false>(sm.e, in, out, g, x0, y0, z0, z1, gate,
+                                                    inv9n);
 }
 
 }  // namespace lnf

@@ -84,8 +84,11 @@ def test_small_phantom_64cube_u8(filters, rule, r, seed):
     _assert_same(got, want, vol, r, f"64^3 u8 seed {seed} r={r} {rule}")
 
 
+# odd and even row lengths: even ones take the paired staging, whose tiles at
+# the x faces substitute the edge element (tiles covering one face or both)
 ODD_DIMS = [(1, 1, 1), (1, 1, 7), (7, 1, 1), (1, 9, 1), (2, 3, 5), (13, 11, 7), (17, 1, 3),
-            (65, 17, 9), (64, 16, 8), (63, 15, 31), (97, 35, 21)]
+            (65, 17, 9), (64, 16, 8), (63, 15, 31), (97, 35, 21), (4, 7, 3), (6, 5, 9),
+            (34, 9, 11), (66, 20, 10), (128, 3, 5), (96, 35, 21)]
 
 
 @pytest.mark.parametrize("rule", ["mean9", "minvar9"])
@@ -243,3 +246,21 @@ def test_reserved_flags_rejected():
     for flags in (1, 2, 0x80000000):
         opt = _lib.lnf_options(ctypes.sizeof(_lib.lnf_options), 0, 0, -1, flags)
         assert _lib.lib().lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_misaligned_base_takes_elementwise_staging(dtype):
+    """A volume whose base is not aligned to a pair of elements (a view one
+    element into a buffer) is staged element by element; results identical."""
+    from paper_1807_03119_amd.api import Filter
+    vol = ph.random_volume((70, 21, 13), dtype, seed=77)
+    n = vol.size
+    tdt = torch.uint8 if dtype == np.uint8 else torch.uint16
+    buf = torch.zeros(n + 1, dtype=tdt, device="cuda")
+    buf[1:].copy_(torch.from_numpy(vol.reshape(-1)).cuda())
+    view = buf[1:].view(vol.shape)  # base one element past an aligned address
+    with Filter(_lib.LNF_MEAN9, 0) as f:
+        for r in (1, 2, 3, 4):
+            want = oracle.filter_volume(vol, r)
+            got = f(view, r).cpu().numpy()
+            _assert_same(got, want, vol, r, f"misaligned {dtype.__name__} r={r}")
