@@ -24,10 +24,12 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
 DIMS = (512, 512, 512)
 SEED = 2000
-# Measured HBM bytes per launch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE,
-# scaled by the counters' reading for a device copy of known size), per
-# (rule, radius).  None until taken for the current kernel.
-TRAFFIC_BYTES = {}
+# Measured HBM bytes per launch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, each
+# scaled by what it reads for the device copy of known size that this script
+# times), per (rule, radius), for the kernels as they stand; the summaries with
+# the commands are profiles/mean9_stream_r3_512cube_u16.txt and
+# profiles/minvar9_planes_r3_512cube_u16.txt.  Absent: not measured.
+TRAFFIC_BYTES = {("mean9", 3): 649755164, ("minvar9", 3): 657644583}
 
 
 def log(msg):

@@ -58,8 +58,8 @@ struct M9Shape {
     static constexpr int LXW = LXE / EPW;           // LDS words holding them (LXE even)
     // Raw row pitch in words: padded to 4 mod 8, so that eight consecutive
     // rows start in eight different groups of four LDS banks (the x-pass reads
-    // 16 bytes per lane, eight lanes per bank cycle).  The padding words are
-    // loaded like halo (clamped) and never used.
+    // 16 bytes per lane, eight lanes per bank cycle).  The padding words repeat
+    // the row's last word and are never used.
     static constexpr int LX = LXW + (12 - LXW % 8) % 8;
     static constexpr int LY = TY + 2 * H;
     static constexpr int NRAW = LX * LY;            // staged words per slice
@@ -110,7 +110,9 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK>& sm,
 #pragma unroll
     for (int i = 0; i < S::NLOAD; ++i) {
         const int e = min(tid + i * S::THREADS, S::NRAW - 1);
-        const int row = e / LX, col = e - row * LX;
+        const int row = e / LX;
+        // padding words re-read the row's last word: no extra cache lines
+        const int col = min(e - row * LX, S::LXW - 1);
         const int gy = clampi(y0 - H + row, 0, g.ny - 1);
         const int gx = clampi(x0 - H + EPW * col, 0, g.nx - EPW);  // even when PK
         off[i] = (uint32_t)(gy * g.nx + gx) * (uint32_t)sizeof(T);
