@@ -63,7 +63,7 @@ def copy_bandwidth(nbytes, stream):
 
 
 def batch_benchmark(rule_code, stream, steps=5):
-    """64 mixed volumes (axes 64..384, uint8/uint16, r in 1..3): one graph launch
+    """64 mixed volumes (axes 64..384, uint8/uint16, r in 1..3): one batch call
     of the batch path against one tuned launch per volume on the same stream."""
     import torch
     from paper_1807_03119_amd import phantom

@@ -136,16 +136,16 @@ typedef struct {
 #define LNF_BATCH_MAX 4096 /* most jobs one lnf_filter_batch call accepts */
 
 /*
- * Filter n volumes with the context's rule and gate in ONE graph launch: the
- * tiles of all jobs go to one persistent kernel per radius class, whose
- * workgroups pull tiles from an atomic work queue until it is empty.  Each
- * output is byte-identical to lnf_filter on the same job.  The job table is
- * copied to the device by the graph itself, so `jobs` may be reused as soon as
- * the call returns; the buffers must stay valid until the work completes on
- * `stream`.  n == 0 is a no-op.
+ * Filter n volumes with the context's rule and gate in one call: the jobs are
+ * grouped by (radius, dtype), and each group runs as ONE kernel launch over the
+ * tiles of all its volumes (larger volumes first), after one copy of the job
+ * table; everything is enqueued on `stream`.  Each output is byte-identical to
+ * lnf_filter on the same job.  The job table is copied by the call, so `jobs`
+ * may be reused as soon as it returns; the buffers must stay valid until the
+ * work completes on `stream`.  n == 0 is a no-op.
  * Errors: LNF_EINVAL (n < 0 or > LNF_BATCH_MAX, a bad job, jobs whose outputs
- * overlap any input or output), LNF_EDEVICE, LNF_ENOMEM, LNF_EHIP.  On error
- * nothing is launched.
+ * overlap any input or output), LNF_EDEVICE, LNF_ENOMEM, LNF_EHIP.  Argument
+ * errors are found before anything is enqueued.
  */
 LNF_API int lnf_filter_batch(lnf_handle h, const lnf_job* jobs, int n, hipStream_t stream);
 
@@ -208,8 +208,10 @@ LNF_API int lnf_filter_points(lnf_handle h, const void* vol, const int64_t dims[
 /*
  * A request server with continuous batching.  Volumes are uploaded once and
  * stay resident in library-owned device memory; filter requests against them
- * (at any radius) are queued, admitted while the device footprint (resident
- * volumes + request outputs + cached blocks) stays under the cap, grouped
+ * (at any radius) are queued, admitted while their memory fits under the cap
+ * (the server holds at most cap_bytes of device memory, allocated in chunks as
+ * needed and kept until lnf_server_destroy; volumes and request outputs take
+ * ranges of it, so evictions never free device memory), grouped
  * into micro-batches of everything admitted so far, and launched through the
  * batch path on a pool of streams, so batches issued while others run overlap
  * on the device.  Idle volumes are evicted least-recently-used first when the
@@ -237,7 +239,7 @@ typedef struct {
 typedef struct {
     uint64_t submitted, completed, failed, cancelled, batches, evictions, uploads;
     uint64_t voxels;          /* voxels filtered by completed requests */
-    uint64_t bytes_in_use;    /* current device footprint */
+    uint64_t bytes_in_use;    /* current device footprint (memory the server holds) */
     uint64_t peak_bytes;      /* largest footprint seen */
     double p50_ms, p99_ms, max_ms, mean_ms;  /* latency of completed requests */
     double busy_s;            /* first arrival to last completion */

@@ -81,8 +81,8 @@ class Filter:
         return hist
 
     def batch(self, items, stream=None):
-        """Filter [(vol, radius), ...] (or [(vol, out, radius), ...]) in one graph
-        launch; returns the list of outputs."""
+        """Filter [(vol, radius), ...] (or [(vol, out, radius), ...]) with one
+        launch per (radius, dtype) group; returns the list of outputs."""
         import torch
         triples = []
         for it in items:

@@ -1,15 +1,20 @@
-// Batched filtering: many volumes of mixed size, dtype and radius in one graph
-// launch.  The tiles of all jobs with the same radius form one work queue; a
-// persistent kernel per radius class (the tile body is specialised on r) lets
-// every workgroup pull tiles with an atomic counter until the queue is empty,
-// so the GPU stays full across job boundaries instead of draining at the end
-// of every volume.  The four class kernels are parallel branches of the graph.
+// Batched filtering: many volumes of mixed size, dtype and radius in one call.
 //
-// The graph of a context is built once per staging slot:
-//     H2D copy of the job table  ->  {class kernel r=1, r=2, r=3, r=4}
-// and reused for every batch: only the host-side table and the copy size
-// change between launches.  The queue counters live in the table, so the copy
-// itself resets them (no memset node).
+// The jobs are grouped into classes of equal (radius, voxel type).  Each class
+// runs as ONE kernel launch over the tiles of all its volumes: workgroup b
+// takes tile b of the class (XCD-aware order), finds its volume by binary
+// search over the jobs' first-tile indices, and runs the same streaming tile
+// body as the single-volume kernels (same registers, same occupancy).  The
+// hardware dispatcher then keeps the GPU full across volume boundaries, and a
+// class pays one launch and one tail instead of one per volume.  Larger
+// volumes come first in a class, so its tail consists of small tiles.
+//
+// Per call: one H2D copy of the job table (from one of four pinned staging
+// slots) and one launch per non-empty class, all on the caller's stream.
+// These are plain launches rather than a graph: with this runtime a graph of a
+// copy and one kernel costs about 15 us per launch and parallel kernel
+// branches 45-95 us, against about 5 us for the copy and a kernel launched
+// directly.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,150 +36,142 @@ namespace lnf {
 struct BatchJobDesc {
     const void* in;
     void* out;
-    int nx, ny, nz, dtype;
-    int tiles_x, tiles_y, zs, tile_begin;  // tile_begin: first tile in its class queue
+    int nx, ny, nz;
+    int tiles_x, tiles_y, zs, tile_begin;  // tile_begin: first tile in its class
     int pairs;                             // MEAN9 stages element pairs (mean9_pairs_ok)
 };
 
-struct BatchQueue {
+struct BatchClass {
     int total;      // tiles in this class
     int njobs;      // jobs in this class
     int job_begin;  // index of its first job in `jobs`
-    int counter;    // next tile to hand out (reset to 0 by the upload)
+    int variant;    // MEAN9 tile variant of the class
 };
 
+constexpr int kClasses = 2 * LNF_RADIUS_MAX;  // (radius, voxel type)
+
+// Class of a (radius, dtype) pair.
+constexpr int batch_class(int r, int dtype) { return 2 * (r - 1) + (dtype == LNF_U16 ? 1 : 0); }
+
 struct BatchTable {
-    BatchQueue q[LNF_RADIUS_MAX];
+    BatchClass c[kClasses];
     BatchJobDesc jobs[LNF_BATCH_MAX];
 };
 
 namespace {
 
 constexpr int kSlots = 4;
-constexpr int kMean9TY = 16;  // batch tiles use the 64 x 16 streaming body
 
-// Thread 0 takes the next tile of the class queue and finds its job by binary
-// search over the jobs' first-tile indices; the pair is broadcast through LDS.
-__device__ __forceinline__ bool next_tile(BatchTable* tab, BatchQueue* q, int* s_tile,
-                                          int* s_job, int* tile, int* job)
+// Job of class tile t: the last job whose first tile is <= t (uniform per
+// workgroup, so these are scalar loads).
+__device__ __forceinline__ const BatchJobDesc& job_of(const BatchTable* tab, const BatchClass& c,
+                                                      int t)
 {
-    if (threadIdx.x == 0) {
-        const int t = atomicAdd(&q->counter, 1);
-        int j = -1;
-        if (t < q->total) {
-            int lo = q->job_begin, hi = q->job_begin + q->njobs - 1;
-            while (lo < hi) {  // last job with tile_begin <= t
-                const int mid = (lo + hi + 1) >> 1;
-                if (tab->jobs[mid].tile_begin <= t) lo = mid;
-                else hi = mid - 1;
-            }
-            j = lo;
-        }
-        *s_tile = t;
-        *s_job = j;
+    int lo = c.job_begin, hi = c.job_begin + c.njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab->jobs[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
     }
-    __syncthreads();
-    *tile = *s_tile;
-    *job = *s_job;
-    __syncthreads();
-    return *job >= 0;
+    return tab->jobs[lo];
 }
 
-template <int R, bool GATE>
-__global__ __launch_bounds__((M9Shape<R, kMean9TY>::THREADS)) void mean9_batch(BatchTable* tab,
-                                                                             uint32_t gate)
+template <int R, int TY, typename T, bool GATE, int TXW>
+__global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS)) void mean9_multi(
+    const BatchTable* __restrict__ tab, int cls, uint32_t gate)
 {
-    __shared__ __align__(16) M9SmemAny<R, kMean9TY> sm;
-    __shared__ int s_tile, s_job;
+    __shared__ __align__(16) M9SmemAny<R, TY, TXW> sm;
     constexpr int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
-    const double inv9n = 1.0 / (9.0 * n);
-    BatchQueue* q = &tab->q[R - 1];
-    int t, j;
-    while (next_tile(tab, q, &s_tile, &s_job, &t, &j)) {
-        const BatchJobDesc d = tab->jobs[j];
-        const int local = t - d.tile_begin;
-        const int bx = local % d.tiles_x;
-        const int rest = local / d.tiles_x;
-        const int by = rest % d.tiles_y;
-        const int bz = rest / d.tiles_y;
-        const Geom g{d.nx, d.ny, d.nz};
-        const int z0 = bz * d.zs, z1 = min(z0 + d.zs, d.nz);
-        const int x0 = bx * 64, y0 = by * kMean9TY;
-        if (d.dtype == LNF_U8)
-            mean9_tile<R, kMean9TY, uint8_t, GATE>(sm, d.pairs != 0, (const uint8_t*)d.in,
-                                                   (uint8_t*)d.out, g, x0, y0, z0, z1, gate,
-                                                   inv9n);
-        else
-            mean9_tile<R, kMean9TY, uint16_t, GATE>(sm, d.pairs != 0, (const uint16_t*)d.in,
-                                                    (uint16_t*)d.out, g, x0, y0, z0, z1, gate,
-                                                    inv9n);
-    }
+    const BatchClass c = tab->c[cls];
+    const int t = xcd_tile(blockIdx.x, c.total);
+    const BatchJobDesc d = job_of(tab, c, t);
+    const int local = t - d.tile_begin;
+    const int bx = local % d.tiles_x;
+    const int rest = local / d.tiles_x;
+    const int by = rest % d.tiles_y;
+    const int bz = rest / d.tiles_y;
+    const Geom g{d.nx, d.ny, d.nz};
+    const int z0 = bz * d.zs;
+    mean9_tile<R, TY, T, GATE, TXW>(sm, d.pairs != 0, static_cast<const T*>(d.in),
+                                    static_cast<T*>(d.out), g, bx * TXW, by * TY, z0,
+                                    min(z0 + d.zs, d.nz), gate, 1.0 / (9.0 * n));
 }
 
-template <int R, bool GATE>
-__global__ __launch_bounds__(256) void minvar9_batch(BatchTable* tab, uint32_t gate)
+template <int R, typename T, bool GATE>
+__global__ __launch_bounds__(256) void minvar9_multi(const BatchTable* __restrict__ tab, int cls,
+                                                     uint32_t gate)
 {
     __shared__ __align__(16) MV9Smem<R> sm;
-    __shared__ int s_tile, s_job;
     constexpr int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
-    const double dn = (double)n, invn = 1.0 / n;
-    BatchQueue* q = &tab->q[R - 1];
-    int t, j;
-    while (next_tile(tab, q, &s_tile, &s_job, &t, &j)) {
-        const BatchJobDesc d = tab->jobs[j];
-        const int local = t - d.tile_begin;
-        const int bx = local % d.tiles_x;
-        const int rest = local / d.tiles_x;
-        const int by = rest % d.tiles_y;
-        const int bz = rest / d.tiles_y;
-        const Geom g{d.nx, d.ny, d.nz};
-        const int z0 = bz * d.zs, z1 = min(z0 + d.zs, d.nz);
-        if (d.dtype == LNF_U8)
-            minvar9_tile<R, uint8_t, GATE>(sm, (const uint8_t*)d.in, (uint8_t*)d.out, g, bx * 32,
-                                           by * 8, z0, z1, gate, dn, invn);
-        else
-            minvar9_tile<R, uint16_t, GATE>(sm, (const uint16_t*)d.in, (uint16_t*)d.out, g,
-                                            bx * 32, by * 8, z0, z1, gate, dn, invn);
+    const BatchClass c = tab->c[cls];
+    const int t = xcd_tile(blockIdx.x, c.total);
+    const BatchJobDesc d = job_of(tab, c, t);
+    const int local = t - d.tile_begin;
+    const int bx = local % d.tiles_x;
+    const int rest = local / d.tiles_x;
+    const int by = rest % d.tiles_y;
+    const int bz = rest / d.tiles_y;
+    const Geom g{d.nx, d.ny, d.nz};
+    const int z0 = bz * d.zs;
+    minvar9_tile<R, T, GATE>(sm, static_cast<const T*>(d.in), static_cast<T*>(d.out), g, bx * 32,
+                             by * 8, z0, min(z0 + d.zs, d.nz), gate, (double)n, 1.0 / n);
+}
+
+// A launchable class kernel: function, block size.
+struct ClassKernel {
+    const void* fn = nullptr;
+    int threads = 0;
+};
+
+template <int R, typename T, bool GATE, int TY, int TXW>
+ClassKernel mean9_kernel()
+{
+    return {reinterpret_cast<const void*>(mean9_multi<R, TY, T, GATE, TXW>),
+            M9Shape<R, TY, TXW>::THREADS};
+}
+
+template <int R, typename T, bool GATE>
+ClassKernel mean9_kernel_v(int variant)
+{
+    switch (variant) {
+    case 2: return mean9_kernel<R, T, GATE, 32, 64>();
+    case 3: return mean9_kernel<R, T, GATE, 16, 32>();
+    case 4: return mean9_kernel<R, T, GATE, 32, 32>();
+    default: return mean9_kernel<R, T, GATE, 16, 64>();  // variants 0 and 1: 64 x 16
     }
 }
 
-using BatchKernel = void (*)(BatchTable*, uint32_t);
-
-BatchKernel batch_kernel(int rule, int r, bool gate)
+template <int R, typename T>
+ClassKernel class_kernel_rt(int rule, bool gate, int variant)
 {
-#define LNF_PICK(K)                                                                  \
-    switch (r) {                                                                     \
-    case 1: return gate ? (BatchKernel)K<1, true> : (BatchKernel)K<1, false>;         \
-    case 2: return gate ? (BatchKernel)K<2, true> : (BatchKernel)K<2, false>;         \
-    case 3: return gate ? (BatchKernel)K<3, true> : (BatchKernel)K<3, false>;         \
-    default: return gate ? (BatchKernel)K<4, true> : (BatchKernel)K<4, false>;        \
-    }
-    if (rule == LNF_MEAN9) {
-        LNF_PICK(mean9_batch)
-    }
-    LNF_PICK(minvar9_batch)
-#undef LNF_PICK
+    if (rule == LNF_MEAN9)
+        return gate ? mean9_kernel_v<R, T, true>(variant) : mean9_kernel_v<R, T, false>(variant);
+    if (gate) return {reinterpret_cast<const void*>(minvar9_multi<R, T, true>), 256};
+    return {reinterpret_cast<const void*>(minvar9_multi<R, T, false>), 256};
 }
 
-int batch_threads(int rule, int r)
+template <typename T>
+ClassKernel class_kernel_t(int rule, int r, bool gate, int variant)
 {
-    if (rule == LNF_MEAN9) {
-        switch (r) {
-        case 1: return M9Shape<1, kMean9TY>::THREADS;
-        case 2: return M9Shape<2, kMean9TY>::THREADS;
-        case 3: return M9Shape<3, kMean9TY>::THREADS;
-        default: return M9Shape<4, kMean9TY>::THREADS;
-        }
+    switch (r) {
+    case 1: return class_kernel_rt<1, T>(rule, gate, variant);
+    case 2: return class_kernel_rt<2, T>(rule, gate, variant);
+    case 3: return class_kernel_rt<3, T>(rule, gate, variant);
+    default: return class_kernel_rt<4, T>(rule, gate, variant);
     }
-    return 256;
+}
+
+// Kernel of class c (= batch_class(r, dtype)) for a tile variant.
+ClassKernel class_kernel(int rule, int c, bool gate, int variant)
+{
+    const int r = c / 2 + 1;
+    return (c & 1) ? class_kernel_t<uint16_t>(rule, r, gate, variant)
+                   : class_kernel_t<uint8_t>(rule, r, gate, variant);
 }
 
 struct BatchSlot {
     BatchTable* host = nullptr;  // pinned staging copy of the table
     BatchTable* dev = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy = nullptr;
     hipEvent_t done = nullptr;
     bool pending = false;
 };
@@ -185,7 +182,6 @@ struct BatchState {
     std::mutex mu;
     BatchSlot slot[kSlots];
     int next = 0;
-    int grid[LNF_RADIUS_MAX] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -196,14 +192,12 @@ void free_slot(BatchSlot& s)
         (void)hipEventSynchronize(s.done);
         (void)hipEventDestroy(s.done);
     }
-    if (s.exec) (void)hipGraphExecDestroy(s.exec);
-    if (s.graph) (void)hipGraphDestroy(s.graph);
     if (s.dev) (void)hipFree(s.dev);
     if (s.host) (void)hipHostFree(s.host);
     s = BatchSlot{};
 }
 
-int build_slot(const lnf_ctx* h, BatchState* st, BatchSlot& s)
+int build_slot(BatchSlot& s)
 {
     if (hipHostMalloc((void**)&s.host, sizeof(BatchTable), hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void**)&s.dev, sizeof(BatchTable)) != hipSuccess) {
@@ -212,54 +206,8 @@ int build_slot(const lnf_ctx* h, BatchState* st, BatchSlot& s)
     }
     std::memset(s.host, 0, sizeof(BatchTable));
     if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return LNF_EHIP;
-    if (hipGraphCreate(&s.graph, 0) != hipSuccess) return LNF_EHIP;
-    if (hipGraphAddMemcpyNode1D(&s.copy, s.graph, nullptr, 0, s.dev, s.host, sizeof(BatchTable),
-                                hipMemcpyHostToDevice) != hipSuccess)
-        return LNF_EHIP;
-    const bool gate = h->gate != 0;
-    for (int r = 1; r <= LNF_RADIUS_MAX; ++r) {
-        BatchTable* tab = s.dev;
-        uint32_t g = h->gate;
-        void* args[] = {&tab, &g};
-        hipKernelNodeParams p{};
-        p.func = reinterpret_cast<void*>(batch_kernel(h->rule, r, gate));
-        p.gridDim = dim3(st->grid[r - 1]);
-        p.blockDim = dim3(batch_threads(h->rule, r));
-        p.sharedMemBytes = 0;
-        p.kernelParams = args;
-        p.extra = nullptr;
-        hipGraphNode_t kn;
-        if (hipGraphAddKernelNode(&kn, s.graph, &s.copy, 1, &p) != hipSuccess) return LNF_EHIP;
-    }
-    if (hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0) != hipSuccess) return LNF_EHIP;
     return LNF_OK;
 }
-
-int init_batch_state(lnf_ctx* h, BatchState** out)
-{
-    BatchState* st = new (std::nothrow) BatchState();
-    if (!st) return LNF_ENOMEM;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, h->device) != hipSuccess) {
-        delete st;
-        return LNF_EHIP;
-    }
-    for (int r = 1; r <= LNF_RADIUS_MAX; ++r) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(batch_kernel(h->rule, r, h->gate != 0)),
-                batch_threads(h->rule, r), 0) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        st->grid[r - 1] = prop.multiProcessorCount * per_cu;
-    }
-    *out = st;
-    return LNF_OK;
-}
-
-// Default z-strip depth of a batch job: deep enough to keep the z-halo small,
-// shallow enough to give the queue many tiles for load balance.
-int batch_default_zs(int nz) { return std::min(nz, 128); }
 
 }  // namespace
 
@@ -305,69 +253,105 @@ int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>
     {
         std::lock_guard<std::mutex> lk(h->mu);
         if (!h->batch) {
-            BatchState* st = nullptr;
-            const int rc = init_batch_state(h, &st);
-            if (rc) return rc;
-            h->batch = st;
+            h->batch = new (std::nothrow) BatchState();
+            if (!h->batch) return LNF_ENOMEM;
         }
     }
     BatchState* st = h->batch;
     std::lock_guard<std::mutex> lk(st->mu);
     BatchSlot& s = st->slot[st->next];
     st->next = (st->next + 1) % kSlots;
-    if (!s.exec) {
-        const int rc = build_slot(h, st, s);
+    if (!s.host) {
+        const int rc = build_slot(s);
         if (rc) {
             free_slot(s);
             return rc;
         }
     }
+    // the slot's previous table may still be read by its kernels
     if (s.pending && hipEventSynchronize(s.done) != hipSuccess) return LNF_EHIP;
     s.pending = false;
 
-    // order: by class, then larger jobs first (their tiles enter the queue first)
+    // order: by class, then larger jobs first (their tiles get the low indices)
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
+    auto vox = [&](int i) { return (double)geoms[i].nx * geoms[i].ny * geoms[i].nz; };
     std::sort(order.begin(), order.end(), [&](int a, int b) {
-        if (jobs[a].radius != jobs[b].radius) return jobs[a].radius < jobs[b].radius;
-        const double va = (double)geoms[a].nx * geoms[a].ny * geoms[a].nz;
-        const double vb = (double)geoms[b].nx * geoms[b].ny * geoms[b].nz;
-        if (va != vb) return va > vb;
+        const int ca = batch_class(jobs[a].radius, jobs[a].dtype);
+        const int cb = batch_class(jobs[b].radius, jobs[b].dtype);
+        if (ca != cb) return ca < cb;
+        if (vox(a) != vox(b)) return vox(a) > vox(b);
         return a < b;
     });
     BatchTable* tab = s.host;
-    std::memset(tab->q, 0, sizeof(tab->q));
-    int tx = 64, ty = 16;
-    if (h->rule == LNF_MEAN9) mean9_tile_shape(1, &tx, &ty);
-    else minvar9_tile_shape(0, &tx, &ty);
-    for (int k = 0; k < n; ++k) {
-        const int i = order[k];
-        const Geom& g = geoms[i];
-        BatchQueue& q = tab->q[jobs[i].radius - 1];
-        if (q.njobs == 0) q.job_begin = k;
-        BatchJobDesc& d = tab->jobs[k];
-        d.in = jobs[i].in;
-        d.out = jobs[i].out;
-        d.nx = g.nx;
-        d.ny = g.ny;
-        d.nz = g.nz;
-        d.dtype = jobs[i].dtype;
-        d.pairs = mean9_pairs_ok(d.in, g.nx, jobs[i].dtype == LNF_U8 ? 1 : 2) ? 1 : 0;
-        const TileCfg cfg = ctx_tile(h, h->rule, jobs[i].dtype, jobs[i].radius, g);
-        d.zs = cfg.zs > 0 ? std::min(cfg.zs, g.nz) : batch_default_zs(g.nz);
-        d.tiles_x = (g.nx + tx - 1) / tx;
-        d.tiles_y = (g.ny + ty - 1) / ty;
-        const long long tiles = (long long)d.tiles_x * d.tiles_y * ((g.nz + d.zs - 1) / d.zs);
-        if ((long long)q.total + tiles > INT32_MAX) return LNF_EINVAL;
-        d.tile_begin = q.total;
-        q.total += (int)tiles;
-        q.njobs += 1;
+    ClassKernel kern[kClasses];
+    int k = 0;
+    for (int c = 0; c < kClasses; ++c) {
+        BatchClass& cl = tab->c[c];
+        cl = BatchClass{0, 0, k, 0};
+        int kend = k;
+        while (kend < n && batch_class(jobs[order[kend]].radius, jobs[order[kend]].dtype) == c)
+            ++kend;
+        if (kend == k) continue;
+        const int r = c / 2 + 1, dtype = (c & 1) ? LNF_U16 : LNF_U8;
+        // tile variant: the tuned one of the class's largest volume, else the
+        // default for (dtype, r)
+        int variant = 0, tx = 32, ty = 8;
+        if (h->rule == LNF_MEAN9) {
+            const TileCfg cfg = ctx_tile(h, h->rule, dtype, r, geoms[order[k]]);
+            variant = cfg.variant >= 1 && cfg.variant < mean9_variants()
+                          ? cfg.variant
+                          : mean9_default_variant(dtype, r);
+            mean9_tile_shape(variant, &tx, &ty);
+        } else {
+            minvar9_tile_shape(0, &tx, &ty);
+        }
+        kern[c] = class_kernel(h->rule, c, h->gate != 0, variant);
+        // z-strips: enough tiles in the class for one full round of resident
+        // workgroups, strips no shallower than 16 slices
+        long long cols = 0;
+        for (int q = k; q < kend; ++q) {
+            const Geom& g = geoms[order[q]];
+            cols += (long long)((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
+        }
+        const long long target = resident_groups(kern[c].fn, kern[c].threads);
+        const int nzs_want = (int)std::min<long long>(1 << 20, std::max<long long>(1, (target + cols - 1) / cols));
+        for (int q = k; q < kend; ++q) {
+            const int i = order[q];
+            const Geom& g = geoms[i];
+            BatchJobDesc& d = tab->jobs[q];
+            d.in = jobs[i].in;
+            d.out = jobs[i].out;
+            d.nx = g.nx;
+            d.ny = g.ny;
+            d.nz = g.nz;
+            d.pairs = mean9_pairs_ok(d.in, g.nx, dtype == LNF_U8 ? 1 : 2) ? 1 : 0;
+            const int nzs = std::min(nzs_want, std::max(1, g.nz / 16));
+            d.zs = (g.nz + nzs - 1) / nzs;
+            d.tiles_x = (g.nx + tx - 1) / tx;
+            d.tiles_y = (g.ny + ty - 1) / ty;
+            const long long tiles = (long long)d.tiles_x * d.tiles_y * ((g.nz + d.zs - 1) / d.zs);
+            if ((long long)cl.total + tiles > INT32_MAX) return LNF_EINVAL;
+            d.tile_begin = cl.total;
+            cl.total += (int)tiles;
+        }
+        cl.njobs = kend - k;
+        cl.variant = variant;
+        k = kend;
     }
     const size_t used = offsetof(BatchTable, jobs) + (size_t)std::max(n, 1) * sizeof(BatchJobDesc);
-    if (hipGraphExecMemcpyNodeSetParams1D(s.exec, s.copy, s.dev, s.host, used,
-                                          hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpyAsync(s.dev, s.host, used, hipMemcpyHostToDevice, stream) != hipSuccess)
         return LNF_EHIP;
-    if (hipGraphLaunch(s.exec, stream) != hipSuccess) return LNF_EHIP;
+    for (int c = 0; c < kClasses; ++c) {
+        if (tab->c[c].total == 0) continue;
+        const BatchTable* dtab = s.dev;
+        int cls = c;
+        uint32_t gate = h->gate;
+        void* args[] = {&dtab, &cls, &gate};
+        if (hipLaunchKernel(kern[c].fn, dim3(tab->c[c].total), dim3(kern[c].threads), args, 0,
+                            stream) != hipSuccess)
+            return LNF_EHIP;
+    }
     if (hipEventRecord(s.done, stream) != hipSuccess) return LNF_EHIP;
     s.pending = true;
     return LNF_OK;

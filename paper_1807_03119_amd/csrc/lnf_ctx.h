@@ -14,7 +14,7 @@
 
 namespace lnf {
 
-struct BatchState;  // batch.hip: staging slots and graphs of lnf_filter_batch
+struct BatchState;  // batch.hip: job-table staging slots of lnf_filter_batch
 using TuneKey = uint64_t;
 TuneKey tune_key(int rule, int dtype, int radius, Geom g);
 

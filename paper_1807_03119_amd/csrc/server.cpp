@@ -10,9 +10,11 @@
 //     the upload events of its volumes), so later batches overlap earlier ones;
 //   - completion: per-batch events are polled; latency is measured from each
 //     request's scheduled arrival time to the moment its completion is seen.
-// Device blocks are recycled through a cache keyed by geometric size classes
-// (eight per octave), so a steady stream of differently sized volumes rarely
-// reaches hipMalloc / hipFree, which would synchronise the device.
+// Device memory comes from an arena: chunks are allocated on demand up to the
+// cap and kept until the server ends, and volumes and outputs take ranges of
+// them from a best-fit free list that merges neighbours.  Evicting a volume
+// only returns its range, so the steady state never reaches hipFree, which
+// would synchronise the whole device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,22 +45,117 @@ int64_t steady_ns()
         .count();
 }
 
-// Size class: smallest 2^(k/8) multiple of 64 KiB that holds `bytes`.
-size_t size_class(size_t bytes)
-{
-    const size_t unit = 64u << 10;
-    size_t c = unit;
-    while (c < bytes) {
-        size_t next = (size_t)std::ceil((double)c * 1.0905077326652577);  // 2^(1/8)
-        next = (next + unit - 1) / unit * unit;
-        c = std::max(next, c + unit);
+// Device ranges for the server: host-side bookkeeping over chunks that are
+// allocated once and freed only by release_all().  Ranges never span two
+// chunks (each chunk is its own allocation).
+class Arena {
+public:
+    static constexpr size_t kAlign = 64u << 10;  // range granularity
+    static constexpr size_t kChunk = 4ull << 30;  // preferred chunk size
+
+    static size_t round(size_t bytes) { return (bytes + kAlign - 1) / kAlign * kAlign; }
+    size_t reserved() const { return reserved_; }  // device bytes held in chunks
+    size_t used() const { return used_; }          // bytes in ranges handed out
+
+    // Best-fit range of `bytes` (a multiple of kAlign) from free space, or null.
+    void* take(size_t bytes)
+    {
+        auto it = by_size_.lower_bound(bytes);
+        if (it == by_size_.end()) return nullptr;
+        char* p = it->second;
+        const size_t have = it->first;
+        by_size_.erase(it);
+        by_addr_.erase(p);
+        if (have > bytes) insert(p + bytes, have - bytes);
+        used_ += bytes;
+        return p;
     }
-    return c;
-}
+
+    // Return a range; merges with free neighbours inside the same chunk.
+    void give(void* ptr, size_t bytes)
+    {
+        char* p = static_cast<char*>(ptr);
+        used_ -= bytes;
+        const char* chunk_end = chunk_of(p);
+        auto next = by_addr_.find(p + bytes);
+        if (next != by_addr_.end() && p + bytes < chunk_end) {
+            bytes += next->second;
+            erase(next);
+        }
+        auto prev = by_addr_.lower_bound(p);
+        if (prev != by_addr_.begin()) {
+            --prev;
+            if (prev->first + prev->second == p && chunk_of(prev->first) == chunk_end) {
+                p = prev->first;
+                bytes += prev->second;
+                erase(prev);
+            }
+        }
+        insert(p, bytes);
+    }
+
+    // Allocate a chunk of at least `bytes` without the held total passing
+    // `limit`.  hipMalloc does not synchronise the device.
+    int grow(size_t bytes, size_t limit)
+    {
+        if (reserved_ + bytes > limit) return LNF_EBUSY;
+        size_t want = std::min(std::max(kChunk, bytes), limit - reserved_);
+        void* p = nullptr;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            want = bytes;
+            if (hipMalloc(&p, want) != hipSuccess) {
+                (void)hipGetLastError();
+                return LNF_ENOMEM;
+            }
+        }
+        chunks_[static_cast<char*>(p)] = want;
+        reserved_ += want;
+        insert(static_cast<char*>(p), want);
+        return LNF_OK;
+    }
+
+    void release_all()
+    {
+        for (auto& c : chunks_) (void)hipFree(c.first);
+        chunks_.clear();
+        by_addr_.clear();
+        by_size_.clear();
+        reserved_ = used_ = 0;
+    }
+
+private:
+    const char* chunk_of(const char* p) const  // end of the chunk holding p
+    {
+        auto it = chunks_.upper_bound(const_cast<char*>(p));
+        --it;
+        return it->first + it->second;
+    }
+    void insert(char* p, size_t n)
+    {
+        by_addr_[p] = n;
+        by_size_.emplace(n, p);
+    }
+    void erase(std::map<char*, size_t>::iterator it)
+    {
+        auto range = by_size_.equal_range(it->second);
+        for (auto s = range.first; s != range.second; ++s)
+            if (s->second == it->first) {
+                by_size_.erase(s);
+                break;
+            }
+        by_addr_.erase(it);
+    }
+
+    std::map<char*, size_t> chunks_;          // start -> size
+    std::map<char*, size_t> by_addr_;         // free ranges: start -> size
+    std::multimap<size_t, char*> by_size_;    // free ranges: size -> start
+    size_t reserved_ = 0, used_ = 0;
+};
 
 struct Volume {
     void* dev = nullptr;
-    size_t block = 0;  // size class of the device block
+    size_t block = 0;  // bytes of its arena range
     int64_t dims[3] = {0, 0, 0};
     int dtype = 0;
     hipEvent_t ready = nullptr;  // upload complete
@@ -123,10 +220,10 @@ public:
                 (void)hipEventSynchronize(kv.second.ready);
                 (void)hipEventDestroy(kv.second.ready);
             }
-            (void)hipFree(kv.second.dev);
         }
-        for (auto& kv : cache_)
-            for (void* p : kv.second) (void)hipFree(p);
+        for (hipStream_t s : streams_) (void)hipStreamSynchronize(s);
+        if (upload_) (void)hipStreamSynchronize(upload_);
+        arena_.release_all();
         for (hipEvent_t e : free_events_) (void)hipEventDestroy(e);
         for (hipStream_t s : streams_) (void)hipStreamDestroy(s);
         if (upload_) (void)hipStreamDestroy(upload_);
@@ -187,7 +284,7 @@ public:
         auto it = vols_.find(id);
         if (it == vols_.end() || it->second.released) return LNF_ENOTFOUND;
         it->second.released = true;
-        if (it->second.refs == 0) drop_volume(it, false);
+        if (it->second.refs == 0) drop_volume(it);
         return LNF_OK;
     }
 
@@ -273,7 +370,7 @@ public:
         s.evictions = evictions_;
         s.uploads = uploads_;
         s.voxels = voxels_;
-        s.bytes_in_use = used_;
+        s.bytes_in_use = arena_.reserved();
         s.peak_bytes = peak_;
         if (!lat_ms_.empty()) {
             std::vector<double> v = lat_ms_;
@@ -299,63 +396,45 @@ public:
             submitted_ = completed_ = failed_ = cancelled_ = batches_ = evictions_ = uploads_ = 0;
             voxels_ = 0;
             first_arrival_ = last_done_ = 0;
-            peak_ = used_;
+            peak_ = arena_.reserved();
         }
         return LNF_OK;
     }
 
 private:
     // ---- memory -------------------------------------------------------------
+    // A range of `bytes` for a volume or an output: free space first, then a
+    // new chunk while the cap allows, then evicting idle volumes (never `keep`).
     int get_block(size_t bytes, uint64_t keep, void** p, size_t* block)
     {
-        const size_t c = size_class(bytes);
-        auto it = cache_.find(c);
-        if (it != cache_.end() && !it->second.empty()) {
-            *p = it->second.back();
-            it->second.pop_back();
-            *block = c;
-            return LNF_OK;
-        }
-        if (c > o_.cap_bytes) return LNF_EBUSY;
-        while (used_ + c > o_.cap_bytes)
-            if (!drop_one(keep)) return LNF_EBUSY;
-        if (hipMalloc(p, c) != hipSuccess) {
-            (void)hipGetLastError();
-            while (drop_one(keep)) {
+        const size_t n = Arena::round(bytes);
+        if (n > o_.cap_bytes) return LNF_EBUSY;
+        for (;;) {
+            if ((*p = arena_.take(n))) {
+                *block = n;
+                peak_ = std::max(peak_, arena_.reserved());
+                return LNF_OK;
             }
-            if (hipMalloc(p, c) != hipSuccess) {
-                (void)hipGetLastError();
-                return LNF_ENOMEM;
-            }
+            const int rc = arena_.grow(n, o_.cap_bytes);
+            if (rc == LNF_OK) continue;
+            if (rc == LNF_ENOMEM && arena_.reserved() == 0) return LNF_ENOMEM;
+            if (!evict_one(keep)) return LNF_EBUSY;  // wait for requests to finish
         }
-        used_ += c;
-        peak_ = std::max(peak_, used_);
-        *block = c;
-        return LNF_OK;
     }
 
-    void put_block(void* p, size_t c) { cache_[c].push_back(p); }
+    void put_block(void* p, size_t n) { arena_.give(p, n); }
 
-    // Release one cached block, or else evict the least recently used idle volume.
-    bool drop_one(uint64_t keep)
+    // Evict the least recently used idle volume: those whose upload has
+    // finished first, then (waiting for the copy) those still being uploaded.
+    bool evict_one(uint64_t keep)
     {
-        for (auto it = cache_.begin(); it != cache_.end(); ++it) {
-            if (!it->second.empty()) {
-                (void)hipFree(it->second.back());
-                it->second.pop_back();
-                used_ -= it->first;
-                return true;
-            }
-        }
-        // idle volumes whose upload has finished first, then (waiting for the
-        // copy) idle volumes still being uploaded
         for (int pass = 0; pass < 2; ++pass) {
             for (uint64_t id : lru_) {
                 if (id == keep) continue;
                 auto vit = vols_.find(id);
                 if (vit->second.refs > 0) continue;
                 if (pass == 0 && hipEventQuery(vit->second.ready) != hipSuccess) continue;
-                drop_volume(vit, true);  // synchronises on the upload event
+                drop_volume(vit);
                 ++evictions_;
                 return true;
             }
@@ -363,18 +442,13 @@ private:
         return false;
     }
 
-    // Free a volume's block (to the device when evicting, to the cache otherwise).
-    void drop_volume(std::unordered_map<uint64_t, Volume>::iterator it, bool to_device)
+    // Return a volume's range to the arena (after its upload has completed).
+    void drop_volume(std::unordered_map<uint64_t, Volume>::iterator it)
     {
         Volume& v = it->second;
         (void)hipEventSynchronize(v.ready);
         free_events_.push_back(v.ready);
-        if (to_device) {
-            (void)hipFree(v.dev);
-            used_ -= v.block;
-        } else {
-            put_block(v.dev, v.block);
-        }
+        put_block(v.dev, v.block);
         lru_.erase(v.lru);
         vols_.erase(it);
     }
@@ -412,7 +486,7 @@ private:
         auto vit = vols_.find(r.vol);
         if (vit != vols_.end()) {
             vit->second.refs -= 1;
-            if (vit->second.refs == 0 && vit->second.released) drop_volume(vit, false);
+            if (vit->second.refs == 0 && vit->second.released) drop_volume(vit);
         }
         if (status == LNF_OK) {
             ++completed_;
@@ -469,7 +543,7 @@ private:
         int rc = LNF_OK;
         if (o_.fail_batch > 0 && batches_ == (uint64_t)o_.fail_batch) rc = LNF_ECANCELED;
         if (rc == LNF_OK) {
-            // a micro-batch of one is a plain launch: no table upload, no graph
+            // a micro-batch of one is a plain launch: no table upload
             if (o_.mode == LNF_SERVE_FIFO || jobs.size() == 1)
                 rc = lnf_filter(h_, jobs[0].in, jobs[0].dims, jobs[0].dtype, jobs[0].radius,
                                 jobs[0].out, s);
@@ -560,9 +634,9 @@ private:
     std::unordered_map<uint64_t, Request> reqs_;
     std::deque<uint64_t> pending_;
     std::list<Flight> flights_;
-    std::map<size_t, std::vector<void*>> cache_;
+    Arena arena_;
     std::vector<hipEvent_t> free_events_;
-    size_t used_ = 0, peak_ = 0;
+    size_t peak_ = 0;  // largest device footprint (arena chunks) seen
     uint64_t next_vol_ = 1, next_ticket_ = 1;
 
     uint64_t submitted_ = 0, completed_ = 0, failed_ = 0, cancelled_ = 0, batches_ = 0;
