@@ -20,6 +20,12 @@ from .otsu import histogram, otsu_threshold  # noqa: F401
 
 MEAN9 = 0
 MINVAR9 = 1
+BOX = 0      # cubic clusters of side 2r+1
+CROSS = 1    # eq. 2's three lines of 2r+1 voxels through the cluster centre
+# diagonal offset of the eight outer clusters
+OFFSET_R = 0       # d = r
+OFFSET_ONE = 1     # d = 1
+OFFSET_TILE = 2    # d = 2r+1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lnf_oracle.c")
@@ -47,12 +53,18 @@ def _load():
     i64, vp = ctypes.c_int64, ctypes.c_void_p
     lib.lnfo_filter.argtypes = [vp, i64, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                 ctypes.c_uint32, vp]
+    lib.lnfo_filter_geom.argtypes = [vp, i64, i64, i64, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
+                                     vp]
+    lib.lnfo_cluster_stats_geom.argtypes = [vp, i64, i64, i64, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_int, i64, i64, i64, vp, vp]
     lib.lnfo_filter_points.argtypes = [vp, i64, i64, i64, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_uint32, vp, i64, vp]
     lib.lnfo_cluster_stats.argtypes = [vp, i64, i64, i64, ctypes.c_int, ctypes.c_int,
                                        i64, i64, i64, vp, vp]
     lib.lnfo_threads.argtypes = []
-    for f in (lib.lnfo_filter, lib.lnfo_filter_points, lib.lnfo_cluster_stats, lib.lnfo_threads):
+    for f in (lib.lnfo_filter, lib.lnfo_filter_geom, lib.lnfo_filter_points,
+              lib.lnfo_cluster_stats, lib.lnfo_cluster_stats_geom, lib.lnfo_threads):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -66,13 +78,14 @@ def _dtype_code(vol: np.ndarray) -> int:
     raise TypeError(f"oracle takes uint8 or uint16 volumes, got {vol.dtype}")
 
 
-def filter_volume(vol: np.ndarray, r: int, rule: int = MEAN9, gate: int = 0) -> np.ndarray:
-    """Filter a whole [z, y, x] volume."""
+def filter_volume(vol: np.ndarray, r: int, rule: int = MEAN9, gate: int = 0,
+                  shape: int = BOX, offset: int = OFFSET_R) -> np.ndarray:
+    """Filter a whole [z, y, x] volume (cluster shape and diagonal offset as above)."""
     vol = np.ascontiguousarray(vol)
     nz, ny, nx = vol.shape
     out = np.empty_like(vol)
-    rc = _load().lnfo_filter(vol.ctypes.data, nx, ny, nz, _dtype_code(vol), r, rule, gate,
-                             out.ctypes.data)
+    rc = _load().lnfo_filter_geom(vol.ctypes.data, nx, ny, nz, _dtype_code(vol), r, rule, gate,
+                                  shape, offset, out.ctypes.data)
     if rc:
         raise ValueError("oracle rejected the arguments")
     return out
@@ -91,14 +104,15 @@ def filter_points(vol: np.ndarray, r: int, xyz, rule: int = MEAN9, gate: int = 0
     return out
 
 
-def cluster_stats(vol: np.ndarray, r: int, x: int, y: int, z: int):
+def cluster_stats(vol: np.ndarray, r: int, x: int, y: int, z: int, shape: int = BOX,
+                  offset: int = OFFSET_R):
     """(sums[9], sums of squares[9]) of the nine clusters about voxel (x, y, z)."""
     vol = np.ascontiguousarray(vol)
     nz, ny, nx = vol.shape
     s = np.zeros(9, dtype=np.uint64)
     q = np.zeros(9, dtype=np.uint64)
-    rc = _load().lnfo_cluster_stats(vol.ctypes.data, nx, ny, nz, _dtype_code(vol), r, x, y, z,
-                                    s.ctypes.data, q.ctypes.data)
+    rc = _load().lnfo_cluster_stats_geom(vol.ctypes.data, nx, ny, nz, _dtype_code(vol), r, shape,
+                                         offset, x, y, z, s.ctypes.data, q.ctypes.data)
     if rc:
         raise ValueError("oracle rejected the arguments")
     return s, q

@@ -28,7 +28,18 @@
  * n = M^3) are odd; the output has the dtype of the input.
  *
  * Cluster index order: k = 0 is the centre; for k = 1..8, with j = k-1, bit 0
- * of j selects +r (else -r) along x, bit 1 along y, bit 2 along z.
+ * of j selects +d (else -d) along x, bit 1 along y, bit 2 along z.
+ *
+ * Geometry variants (the paper's own open questions, Section "Our Method" and
+ * the conclusion's future work):
+ *   - cluster shape: the cube of side M (the text's "3x3x3 region"), or the
+ *     three-line cross that eq. 2 writes out: the M voxels along x, along y and
+ *     along z through the cluster centre, the centre thus counted three times,
+ *     n = 3M;
+ *   - diagonal offset d of S_1..S_8: r (default; sqrt(3) units at r = 1), 1
+ *     (sqrt(3) units at every r), or 2r+1 (the diagonal clusters just clear
+ *     the centre cluster).
+ * Both divisors stay odd (9n, n with n = M^3 or 3M), so no tie ever occurs.
  *
  * Volume layout: vol[z][y][x], x fastest; dtype 1 = uint8, 2 = uint16.
  */
@@ -37,6 +48,13 @@
 
 #define LNFO_MEAN9 0
 #define LNFO_MINVAR9 1
+#define LNFO_BOX 0
+#define LNFO_CROSS 1
+
+typedef struct {
+    int shape;  /* LNFO_BOX or LNFO_CROSS */
+    int64_t d;  /* diagonal offset of S_1..S_8 */
+} geom_t;
 
 typedef struct {
     const void* vol;
@@ -63,43 +81,62 @@ static uint64_t sample(const grid_t* g, int64_t x, int64_t y, int64_t z)
 }
 
 /* Centre offset of cluster k (see the index order above). */
-static void cluster_offset(int k, int r, int64_t d[3])
+static void cluster_offset(int k, int64_t d, int64_t off[3])
 {
     if (k == 0) {
-        d[0] = d[1] = d[2] = 0;
+        off[0] = off[1] = off[2] = 0;
         return;
     }
     int j = k - 1;
     for (int axis = 0; axis < 3; ++axis)
-        d[axis] = ((j >> axis) & 1) ? r : -r;
+        off[axis] = ((j >> axis) & 1) ? d : -d;
 }
 
-/* Sum and sum of squares of the (2r+1)^3 region of every cluster about (px,py,pz). */
-static void cluster_stats(const grid_t* g, int r, int64_t px, int64_t py, int64_t pz,
-                          uint64_t s[9], uint64_t q[9])
+/* Number of voxels of one cluster, counted with multiplicity. */
+static uint64_t cluster_size(int r, int shape)
+{
+    const uint64_t m = (uint64_t)(2 * r + 1);
+    return shape == LNFO_CROSS ? 3 * m : m * m * m;
+}
+
+/* Sum and sum of squares of every cluster about (px, py, pz): the cube of side
+ * 2r+1, or the three lines of 2r+1 voxels through the cluster centre. */
+static void cluster_stats(const grid_t* g, int r, geom_t geo, int64_t px, int64_t py,
+                          int64_t pz, uint64_t s[9], uint64_t q[9])
 {
     for (int k = 0; k < 9; ++k) {
         int64_t d[3];
-        cluster_offset(k, r, d);
+        cluster_offset(k, geo.d, d);
+        const int64_t cx = px + d[0], cy = py + d[1], cz = pz + d[2];
         uint64_t sum = 0, sq = 0;
-        for (int64_t az = -r; az <= r; ++az)
-            for (int64_t ay = -r; ay <= r; ++ay)
-                for (int64_t ax = -r; ax <= r; ++ax) {
-                    uint64_t v = sample(g, px + d[0] + ax, py + d[1] + ay, pz + d[2] + az);
-                    sum += v;
-                    sq += v * v;
-                }
+        if (geo.shape == LNFO_BOX) {
+            for (int64_t az = -r; az <= r; ++az)
+                for (int64_t ay = -r; ay <= r; ++ay)
+                    for (int64_t ax = -r; ax <= r; ++ax) {
+                        uint64_t v = sample(g, cx + ax, cy + ay, cz + az);
+                        sum += v;
+                        sq += v * v;
+                    }
+        } else {
+            for (int64_t t = -r; t <= r; ++t) {
+                uint64_t vx = sample(g, cx + t, cy, cz);
+                uint64_t vy = sample(g, cx, cy + t, cz);
+                uint64_t vz = sample(g, cx, cy, cz + t);
+                sum += vx + vy + vz;
+                sq += vx * vx + vy * vy + vz * vz;
+            }
+        }
         s[k] = sum;
         q[k] = sq;
     }
 }
 
-static uint32_t filter_voxel(const grid_t* g, int r, int rule, uint32_t gate_T,
+static uint32_t filter_voxel(const grid_t* g, int r, geom_t geo, int rule, uint32_t gate_T,
                              int64_t px, int64_t py, int64_t pz)
 {
     uint64_t s[9], q[9];
-    cluster_stats(g, r, px, py, pz, s, q);
-    const uint64_t n = (uint64_t)(2 * r + 1) * (2 * r + 1) * (2 * r + 1);
+    cluster_stats(g, r, geo, px, py, pz, s, q);
+    const uint64_t n = cluster_size(r, geo.shape);
     uint64_t out;
     if (rule == LNFO_MEAN9) {
         /* mean of the nine cluster means = (sum of all nine sums) / (9n), rounded */
@@ -133,24 +170,44 @@ static int check_args(const void* vol, int64_t nx, int64_t ny, int64_t nz, int d
     return 0;
 }
 
-/* Filter a whole volume; `out` has the dtype and layout of `vol`. */
-int lnfo_filter(const void* vol, int64_t nx, int64_t ny, int64_t nz, int dtype, int r,
-                int rule, uint32_t gate_T, void* out)
+/* shape: LNFO_BOX / LNFO_CROSS; offset_mode 0: d = r, 1: d = 1, 2: d = 2r+1. */
+static int make_geom(int r, int shape, int offset_mode, geom_t* geo)
 {
+    if (shape != LNFO_BOX && shape != LNFO_CROSS) return -1;
+    if (offset_mode < 0 || offset_mode > 2) return -1;
+    geo->shape = shape;
+    geo->d = offset_mode == 0 ? r : offset_mode == 1 ? 1 : 2 * r + 1;
+    return 0;
+}
+
+/* Filter a whole volume with a cluster geometry; `out` has the dtype and
+ * layout of `vol`. */
+int lnfo_filter_geom(const void* vol, int64_t nx, int64_t ny, int64_t nz, int dtype, int r,
+                     int rule, uint32_t gate_T, int shape, int offset_mode, void* out)
+{
+    geom_t geo;
     if (check_args(vol, nx, ny, nz, dtype, r, rule) || !out) return -1;
+    if (make_geom(r, shape, offset_mode, &geo)) return -1;
     grid_t g = {vol, nx, ny, nz, dtype};
     int64_t plane = nx * ny;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t zy = 0; zy < nz * ny; ++zy) {
         int64_t z = zy / ny, y = zy % ny;
         for (int64_t x = 0; x < nx; ++x) {
-            uint32_t v = filter_voxel(&g, r, rule, gate_T, x, y, z);
+            uint32_t v = filter_voxel(&g, r, geo, rule, gate_T, x, y, z);
             int64_t idx = z * plane + y * nx + x;
             if (dtype == 1) ((uint8_t*)out)[idx] = (uint8_t)v;
             else ((uint16_t*)out)[idx] = (uint16_t)v;
         }
     }
     return 0;
+}
+
+/* Filter a whole volume with the default geometry (cubes, d = r). */
+int lnfo_filter(const void* vol, int64_t nx, int64_t ny, int64_t nz, int dtype, int r,
+                int rule, uint32_t gate_T, void* out)
+{
+    return lnfo_filter_geom(vol, nx, ny, nz, dtype, r, rule, gate_T, LNFO_BOX, 0, out);
 }
 
 /* Filter the voxels listed in xyz[m][3] (x, y, z inside the volume) into out[m]. */
@@ -163,20 +220,31 @@ int lnfo_filter_points(const void* vol, int64_t nx, int64_t ny, int64_t nz, int 
         if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) return -1;
     }
     grid_t g = {vol, nx, ny, nz, dtype};
+    const geom_t geo = {LNFO_BOX, r};
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < m; ++i)
-        out[i] = filter_voxel(&g, r, rule, gate_T, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+        out[i] = filter_voxel(&g, r, geo, rule, gate_T, xyz[3 * i], xyz[3 * i + 1],
+                              xyz[3 * i + 2]);
     return 0;
 }
 
 /* The nine (sum, sum of squares) pairs at one voxel, for diagnostics and pins. */
+int lnfo_cluster_stats_geom(const void* vol, int64_t nx, int64_t ny, int64_t nz, int dtype,
+                            int r, int shape, int offset_mode, int64_t x, int64_t y, int64_t z,
+                            uint64_t* s9, uint64_t* q9)
+{
+    geom_t geo;
+    if (check_args(vol, nx, ny, nz, dtype, r, LNFO_MEAN9) || !s9 || !q9) return -1;
+    if (make_geom(r, shape, offset_mode, &geo)) return -1;
+    grid_t g = {vol, nx, ny, nz, dtype};
+    cluster_stats(&g, r, geo, x, y, z, s9, q9);
+    return 0;
+}
+
 int lnfo_cluster_stats(const void* vol, int64_t nx, int64_t ny, int64_t nz, int dtype, int r,
                        int64_t x, int64_t y, int64_t z, uint64_t* s9, uint64_t* q9)
 {
-    if (check_args(vol, nx, ny, nz, dtype, r, LNFO_MEAN9) || !s9 || !q9) return -1;
-    grid_t g = {vol, nx, ny, nz, dtype};
-    cluster_stats(&g, r, x, y, z, s9, q9);
-    return 0;
+    return lnfo_cluster_stats_geom(vol, nx, ny, nz, dtype, r, LNFO_BOX, 0, x, y, z, s9, q9);
 }
 
 /* Number of OpenMP threads a parallel region of this library uses. */

@@ -359,3 +359,137 @@ def test_otsu_separates_bimodal_phantom():
     t = oracle.otsu_threshold(oracle.histogram(vol))
     # background ~20 (sigma 20) and objects 40..220: the cut lies between the modes
     assert 25 < t < 140
+
+
+# ---------------------------------------------------------------------------
+# geometry variants: eq. 2's cross clusters and the diagonal offset d
+# ---------------------------------------------------------------------------
+
+GEOMETRIES = [(shape, off) for shape in (oracle.BOX, oracle.CROSS)
+              for off in (oracle.OFFSET_R, oracle.OFFSET_ONE, oracle.OFFSET_TILE)]
+
+
+def _offset_distance(r, off):
+    return {oracle.OFFSET_R: r, oracle.OFFSET_ONE: 1, oracle.OFFSET_TILE: 2 * r + 1}[off]
+
+
+def _members(r, shape):
+    """Member offsets of one cluster, with multiplicity: the cube, or the three
+    axis lines of eq. 2 (so the centre appears three times)."""
+    span = range(-r, r + 1)
+    if shape == oracle.BOX:
+        return [(a, b, c) for c in span for b in span for a in span]
+    return ([(t, 0, 0) for t in span] + [(0, t, 0) for t in span] + [(0, 0, t) for t in span])
+
+
+def _fraction_filter_geom(vol, r, rule, shape, off):
+    nz, ny, nx = vol.shape
+    d = _offset_distance(r, off)
+    members = _members(r, shape)
+    out = np.zeros_like(vol)
+    for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
+        means, variances = [], []
+        for cx, cy, cz in _centres(d):
+            vals = [int(vol[min(max(z + cz + c, 0), nz - 1),
+                            min(max(y + cy + b, 0), ny - 1),
+                            min(max(x + cx + a, 0), nx - 1)]) for a, b, c in members]
+            m = Fraction(sum(vals), len(vals))
+            means.append(m)
+            variances.append(sum((v - m) ** 2 for v in vals) / len(vals))
+        if rule == oracle.MEAN9:
+            val = round(sum(means) / 9)
+        else:
+            best = min(range(9), key=lambda k: (variances[k], k))
+            val = round(means[best])
+        out[z, y, x] = val
+    return out
+
+
+@pytest.mark.parametrize("shape,off", GEOMETRIES)
+@pytest.mark.parametrize("rule", [oracle.MEAN9, oracle.MINVAR9])
+@pytest.mark.parametrize("r", [1, 2])
+def test_geometry_bruteforce_fractions(shape, off, rule, r):
+    for i, (dims, kind, dtype) in enumerate([((5, 4, 3), "uniform", np.uint8),
+                                             ((4, 3, 4), "low", np.uint16),
+                                             ((3, 3, 3), "extreme", np.uint16)]):
+        vol = ph.random_volume(dims, dtype, seed=100 + 7 * i + r, kind=kind)
+        got = oracle.filter_volume(vol, r, rule, shape=shape, offset=off)
+        want = _fraction_filter_geom(vol, r, rule, shape, off)
+        np.testing.assert_array_equal(got, want, err_msg=f"{dims} {kind} shape {shape} off {off}")
+
+
+def _stamped_kernel(r, shape, off):
+    """Convolution kernel of the nine-cluster sum, built by stamping the cluster
+    shape at the nine centres (library convolution, not the oracle's loops)."""
+    d = _offset_distance(r, off)
+    h = d + r
+    k = np.zeros((2 * h + 1,) * 3, dtype=np.int64)
+    stamp = np.zeros((2 * r + 1,) * 3, dtype=np.int64)
+    if shape == oracle.BOX:
+        stamp[...] = 1
+    else:
+        stamp[r, r, :] += 1  # x line (arrays are [z, y, x])
+        stamp[r, :, r] += 1  # y line
+        stamp[:, r, r] += 1  # z line
+    for sz, sy, sx in [(0, 0, 0)] + list(itertools.product((-1, 1), repeat=3)):
+        cz, cy, cx = h + sz * d, h + sy * d, h + sx * d
+        k[cz - r:cz + r + 1, cy - r:cy + r + 1, cx - r:cx + r + 1] += stamp
+    return k
+
+
+@pytest.mark.parametrize("shape,off", GEOMETRIES)
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_geometry_mean9_equals_stamped_convolution(shape, off, r):
+    vol = ph.small_u8(1000 + r, dims=(19, 17, 13)).astype(np.uint16) * 16
+    k = _stamped_kernel(r, shape, off)
+    n = (2 * r + 1) ** 3 if shape == oracle.BOX else 3 * (2 * r + 1)
+    assert k.sum() == 9 * n
+    s = ndimage.convolve(vol.astype(np.int64), k, mode="nearest")  # nearest = clamp to edge
+    want = ((2 * s + 9 * n) // (18 * n)).astype(np.uint16)
+    got = oracle.filter_volume(vol, r, oracle.MEAN9, shape=shape, offset=off)
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("name,shape,off,h", [
+    ("impulse_mean9_cross_r1.txt", oracle.CROSS, oracle.OFFSET_R, 8100),
+    ("impulse_mean9_box_d3_r1.txt", oracle.BOX, oracle.OFFSET_TILE, 24300),
+])
+def test_geometry_impulse_golden(golden_dir, name, shape, off, h):
+    rows = _read_golden(os.path.join(golden_dir, name))
+    vol = np.zeros((21, 21, 21), dtype=np.uint16)
+    c = 10
+    vol[c, c, c] = h
+    out = oracle.filter_volume(vol, 1, oracle.MEAN9, shape=shape, offset=off)
+    for dx, dy, dz, want in rows:
+        dx, dy, dz = int(dx), int(dy), int(dz)
+        for perm in itertools.permutations((dx, dy, dz)):
+            for sg in itertools.product((-1, 1), repeat=3):
+                px, py, pz = (c + s * d for s, d in zip(sg, perm))
+                assert out[pz, py, px] == int(want), (name, perm, sg)
+
+
+@pytest.mark.parametrize("shape,off", GEOMETRIES)
+@pytest.mark.parametrize("rule", [oracle.MEAN9, oracle.MINVAR9])
+def test_geometry_constant_and_ramp(shape, off, rule):
+    for dims, c in (((1, 1, 1), 9), ((7, 5, 6), 4095)):
+        vol = np.full(dims[::-1], c, dtype=np.uint16)
+        np.testing.assert_array_equal(oracle.filter_volume(vol, 2, rule, shape=shape, offset=off),
+                                      vol)
+    if rule == oracle.MEAN9:
+        # point-symmetric kernel: an affine ramp is reproduced away from the faces
+        r = 2
+        d = _offset_distance(r, off)
+        z, y, x = np.meshgrid(np.arange(20), np.arange(18), np.arange(22), indexing="ij")
+        vol = (100 + 3 * x + 5 * y + 7 * z).astype(np.uint16)
+        out = oracle.filter_volume(vol, r, rule, shape=shape, offset=off)
+        m = d + r
+        np.testing.assert_array_equal(out[m:-m, m:-m, m:-m], vol[m:-m, m:-m, m:-m])
+
+
+def test_geometry_offset_one_is_default_at_r1():
+    vol = ph.small_u8(1001, dims=(12, 11, 10))
+    for shape in (oracle.BOX, oracle.CROSS):
+        for rule in (oracle.MEAN9, oracle.MINVAR9):
+            np.testing.assert_array_equal(
+                oracle.filter_volume(vol, 1, rule, shape=shape, offset=oracle.OFFSET_ONE),
+                oracle.filter_volume(vol, 1, rule, shape=shape, offset=oracle.OFFSET_R))
