@@ -301,6 +301,18 @@ def main():
                 ms2, _ = time_launches(lambda: g(vol, r, out=out), 10, 2, stream)
                 extras[f"{rule_name}_r{r}_Gvox_s"] = nvox / (ms2 * 1e-3) / 1e9
             g.close()
+        log("timing the cluster geometry variants")
+        geoms = {"box_d1": _lib.LNF_GEOM_OFFSET_1, "box_d2r1": _lib.LNF_GEOM_OFFSET_2R1,
+                 "cross_dr": _lib.LNF_GEOM_CROSS,
+                 "cross_d1": _lib.LNF_GEOM_CROSS | _lib.LNF_GEOM_OFFSET_1,
+                 "cross_d2r1": _lib.LNF_GEOM_CROSS | _lib.LNF_GEOM_OFFSET_2R1}
+        for gname, gflags in geoms.items():
+            for rule_name, rc in (("mean9", _lib.LNF_MEAN9), ("minvar9", _lib.LNF_MINVAR9)):
+                g = Filter(rc, 0, geometry=gflags)
+                for r in (1, 3):
+                    ms2, _ = time_launches(lambda: g(vol, r, out=out), 5, 1, stream)
+                    extras[f"geom_{gname}_{rule_name}_r{r}_Gvox_s"] = nvox / (ms2 * 1e-3) / 1e9
+                g.close()
         log("timing the 64-volume mixed batch")
         extras["batch64"] = batch_benchmark(rule_code, stream)
         res["extras"] = extras

@@ -75,14 +75,33 @@ typedef struct {
     int32_t rule;     /* LNF_MEAN9 (default) or LNF_MINVAR9 */
     uint32_t gate_T;  /* data threshold T of the noise gate; 0 disables the gate */
     int32_t device;   /* HIP device ordinal; -1 = the device current at create time */
-    uint32_t flags;   /* reserved, must be 0 */
+    uint32_t flags;   /* cluster geometry: 0 or LNF_GEOM_* bits below */
 } lnf_options;
+
+/*
+ * Cluster geometry (Section "Our Method": eq. 2 writes each cluster as three
+ * lines, the text as a cube; the diagonal distance is given only for M = 3).
+ * Default (flags = 0): cubes of side 2r+1, diagonal centres at (+-r,+-r,+-r).
+ *   LNF_GEOM_CROSS       clusters are the three axis lines of 2r+1 voxels
+ *                        through the centre (eq. 2; n = 3(2r+1), the centre
+ *                        counted on each line);
+ *   LNF_GEOM_OFFSET_1    diagonal centres at (+-1,+-1,+-1) for every r;
+ *   LNF_GEOM_OFFSET_2R1  diagonal centres at (+-(2r+1), ...): the outer
+ *                        clusters just clear the centre one.
+ * The two offset bits exclude each other.  Non-default geometries run on a
+ * general cluster-gather kernel (lnf_filter, lnf_filter_tiled's z-strip depth,
+ * lnf_filter_batch as one launch per job, lnf_filter_otsu, the server);
+ * lnf_filter_points supports the default geometry only.
+ */
+#define LNF_GEOM_CROSS 1u
+#define LNF_GEOM_OFFSET_1 2u
+#define LNF_GEOM_OFFSET_2R1 4u
 
 /*
  * Create a filter context.  opt == NULL gives the defaults (LNF_MEAN9, gate off,
  * current device).  Allocates only library-internal state (a few KB of device
  * memory for the batch descriptor table and the histogram scratch).
- * Errors: LNF_EINVAL (h NULL, bad rule, nonzero flags, size), LNF_EDEVICE (bad device),
+ * Errors: LNF_EINVAL (h NULL, bad rule, unknown or conflicting flags, size), LNF_EDEVICE (bad device),
  * LNF_ENOMEM, LNF_EHIP.
  */
 LNF_API int lnf_create(lnf_handle* h, const lnf_options* opt);
@@ -198,7 +217,8 @@ LNF_API int lnf_filter_otsu(lnf_handle h, const void* vol, const int64_t dims[3]
  * (x, y, z); out: device uint32 [n] receives the filtered value (rule and gate
  * of the context), or 0xFFFFFFFF for a point outside the volume.  Same value
  * as lnf_filter at that voxel.  Asynchronous on `stream`.
- * Errors: LNF_EINVAL, LNF_EDEVICE, LNF_EHIP.
+ * Errors: LNF_EINVAL (also for a context with a non-default cluster geometry),
+ * LNF_EDEVICE, LNF_EHIP.
  */
 LNF_API int lnf_filter_points(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
                               int radius, const int32_t* xyz, int64_t n, uint32_t* out,

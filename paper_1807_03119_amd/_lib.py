@@ -27,6 +27,9 @@ LNF_U8 = 1
 LNF_U16 = 2
 LNF_MEAN9 = 0
 LNF_MINVAR9 = 1
+LNF_GEOM_CROSS = 1
+LNF_GEOM_OFFSET_1 = 2
+LNF_GEOM_OFFSET_2R1 = 4
 LNF_RADIUS_MAX = 4
 
 

@@ -21,11 +21,13 @@ def _require_cuda(t, name):
 class Filter:
     """One lnf context: a rule and a gate threshold on one device."""
 
-    def __init__(self, rule: int = LNF_MEAN9, gate: int = 0, device: int | None = None):
+    def __init__(self, rule: int = LNF_MEAN9, gate: int = 0, device: int | None = None,
+                 geometry: int = 0):
+        """geometry: 0 (cubes, diagonal offset r) or LNF_GEOM_* bits of the C API."""
         import torch
         dev = torch.cuda.current_device() if device is None else int(device)
-        self.rule, self.gate, self.device = rule, int(gate), dev
-        self._h = _lib.lnf_create(rule, int(gate), dev)
+        self.rule, self.gate, self.device, self.geometry = rule, int(gate), dev, int(geometry)
+        self._h = _lib.lnf_create(rule, int(gate), dev, int(geometry))
 
     @property
     def handle(self):

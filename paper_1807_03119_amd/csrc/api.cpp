@@ -131,9 +131,10 @@ TileCfg ctx_tile(const lnf_ctx* h, int rule, int dtype, int radius, Geom g)
     return cfg;
 }
 
-hipError_t launch_rule(int rule, const void* in, void* out, int dtype, int r, Geom g,
-                       uint32_t gate, TileCfg cfg, hipStream_t s)
+hipError_t launch_rule(int rule, uint32_t geom, const void* in, void* out, int dtype, int r,
+                       Geom g, uint32_t gate, TileCfg cfg, hipStream_t s)
 {
+    if (geom) return launch_geometry(rule, geom, in, out, dtype, r, g, gate, cfg.zs, s);
     if (rule == LNF_MEAN9) return launch_mean9(in, out, dtype, r, g, gate, cfg, s);
     return launch_minvar9(in, out, dtype, r, g, gate, cfg, s);
 }
@@ -195,7 +196,10 @@ int lnf_create(lnf_handle* h, const lnf_options* opt)
         o = *opt;
     }
     if (o.rule != LNF_MEAN9 && o.rule != LNF_MINVAR9) return LNF_EINVAL;
-    if (o.flags != 0) return LNF_EINVAL;  // no flags are defined
+    constexpr uint32_t kGeom = LNF_GEOM_CROSS | LNF_GEOM_OFFSET_1 | LNF_GEOM_OFFSET_2R1;
+    if ((o.flags & ~kGeom) ||
+        (o.flags & (LNF_GEOM_OFFSET_1 | LNF_GEOM_OFFSET_2R1)) == (LNF_GEOM_OFFSET_1 | LNF_GEOM_OFFSET_2R1))
+        return LNF_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         (void)hipGetLastError();
@@ -209,6 +213,7 @@ int lnf_create(lnf_handle* h, const lnf_options* opt)
     c->device = dev;
     c->rule = o.rule;
     c->gate = o.gate_T;
+    c->geom = o.flags;
     const int rc = ctx_init_device_state(c);
     if (rc != LNF_OK) {
         delete c;
@@ -257,7 +262,7 @@ int lnf_filter_tiled(lnf_handle h, const void* vol, const int64_t dims[3], int d
     if (!dg.ok()) return LNF_EHIP;
     if ((rc = check_device_range(vol, bytes, h->device))) return rc;
     if ((rc = check_device_range(out, bytes, h->device))) return rc;
-    if (launch_rule(h->rule, vol, out, dtype, radius, g, h->gate, cfg, stream) !=
+    if (launch_rule(h->rule, h->geom, vol, out, dtype, radius, g, h->gate, cfg, stream) !=
         hipSuccess)
         return LNF_EHIP;
     return LNF_OK;

@@ -250,6 +250,15 @@ int validate_jobs(const lnf_ctx* h, const lnf_job* jobs, int n, std::vector<Geom
 int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>& geoms,
                  hipStream_t stream)
 {
+    if (h->geom) {  // geometry variants: the cluster-gather kernel, one launch per job
+        for (int i = 0; i < n; ++i) {
+            const TileCfg cfg = ctx_tile(h, h->rule, jobs[i].dtype, jobs[i].radius, geoms[i]);
+            if (launch_rule(h->rule, h->geom, jobs[i].in, jobs[i].out, jobs[i].dtype,
+                            jobs[i].radius, geoms[i], h->gate, cfg, stream) != hipSuccess)
+                return LNF_EHIP;
+        }
+        return LNF_OK;
+    }
     {
         std::lock_guard<std::mutex> lk(h->mu);
         if (!h->batch) {

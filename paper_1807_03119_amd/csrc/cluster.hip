@@ -1,0 +1,95 @@
+// Geometry variants of the nine-cluster filter (cross clusters of eq. 2, and
+// diagonal offsets 1 or 2r+1): single-volume kernels around the cluster-gather
+// tile of cluster_tile.h.  The default geometry (cubes at offset r) runs on
+// the MEAN9 / MINVAR9 kernels instead.
+#include "cluster_tile.h"
+#include "device_common.h"
+#include "lnf.h"
+#include "lnf_internal.h"
+
+namespace lnf {
+namespace {
+
+template <int R, int D, int SHAPE, bool VAR, typename T>
+__global__ __launch_bounds__(256) void cluster_planes(const T* __restrict__ in,
+                                                      T* __restrict__ out, Geom g, int zs,
+                                                      int tiles_x, int tiles_y, int total,
+                                                      uint32_t gate)
+{
+    using S = CTShape<R, D, SHAPE, VAR>;
+    __shared__ __align__(16) CTSmem<R, D, SHAPE, VAR> sm;
+    const int tile = xcd_tile(blockIdx.x, total);
+    const int bx = tile % tiles_x;
+    const int rest = tile / tiles_x;
+    const int by = rest % tiles_y;
+    const int bz = rest / tiles_y;
+    const int z0 = bz * zs;
+    cluster_tile<R, D, SHAPE, VAR, T>(sm, in, out, g, bx * S::TX, by * S::TY, z0,
+                                      min(z0 + zs, g.nz), gate);
+}
+
+template <int R, int D, int SHAPE, bool VAR, typename T>
+hipError_t launch_geom(const void* in, void* out, Geom g, uint32_t gate, int zs, hipStream_t s)
+{
+    using S = CTShape<R, D, SHAPE, VAR>;
+    const auto kern = cluster_planes<R, D, SHAPE, VAR, T>;
+    const int tiles_x = (g.nx + S::TX - 1) / S::TX, tiles_y = (g.ny + S::TY - 1) / S::TY;
+    if (zs <= 0)
+        zs = default_zs(tiles_x * tiles_y, g.nz, resident_groups((const void*)kern, 256));
+    const int nzs = (g.nz + zs - 1) / zs;
+    const int total = tiles_x * tiles_y * nzs;
+    hipLaunchKernelGGL(kern, dim3(total), dim3(256), 0, s, static_cast<const T*>(in),
+                       static_cast<T*>(out), g, zs, tiles_x, tiles_y, total, gate);
+    return hipGetLastError();
+}
+
+template <int R, int SHAPE, bool VAR, typename T>
+hipError_t launch_offset(int offset, const void* in, void* out, Geom g, uint32_t gate, int zs,
+                         hipStream_t s)
+{
+    switch (offset) {
+    case LNF_GEOM_OFFSET_1: return launch_geom<R, 1, SHAPE, VAR, T>(in, out, g, gate, zs, s);
+    case LNF_GEOM_OFFSET_2R1:
+        return launch_geom<R, 2 * R + 1, SHAPE, VAR, T>(in, out, g, gate, zs, s);
+    default: return launch_geom<R, R, SHAPE, VAR, T>(in, out, g, gate, zs, s);
+    }
+}
+
+template <int R, typename T>
+hipError_t launch_r(int rule, uint32_t geom, const void* in, void* out, Geom g, uint32_t gate,
+                    int zs, hipStream_t s)
+{
+    const int offset = (int)(geom & (LNF_GEOM_OFFSET_1 | LNF_GEOM_OFFSET_2R1));
+    const bool var = rule == LNF_MINVAR9;
+    if (geom & LNF_GEOM_CROSS) {
+        if (var)
+            return launch_offset<R, kClusterCross, true, T>(offset, in, out, g, gate, zs, s);
+        return launch_offset<R, kClusterCross, false, T>(offset, in, out, g, gate, zs, s);
+    }
+    if (var) return launch_offset<R, kClusterBox, true, T>(offset, in, out, g, gate, zs, s);
+    return launch_offset<R, kClusterBox, false, T>(offset, in, out, g, gate, zs, s);
+}
+
+template <typename T>
+hipError_t dispatch(int rule, uint32_t geom, int r, const void* in, void* out, Geom g,
+                    uint32_t gate, int zs, hipStream_t s)
+{
+    switch (r) {
+    case 1: return launch_r<1, T>(rule, geom, in, out, g, gate, zs, s);
+    case 2: return launch_r<2, T>(rule, geom, in, out, g, gate, zs, s);
+    case 3: return launch_r<3, T>(rule, geom, in, out, g, gate, zs, s);
+    case 4: return launch_r<4, T>(rule, geom, in, out, g, gate, zs, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_geometry(int rule, uint32_t geom, const void* in, void* out, int dtype, int r,
+                           Geom g, uint32_t gate, int zs, hipStream_t s)
+{
+    if (dtype == LNF_U8) return dispatch<uint8_t>(rule, geom, r, in, out, g, gate, zs, s);
+    return dispatch<uint16_t>(rule, geom, r, in, out, g, gate, zs, s);
+}
+
+}  // namespace lnf

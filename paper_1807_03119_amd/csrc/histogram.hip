@@ -248,8 +248,8 @@ extern "C" int lnf_filter_otsu(lnf_handle h, const void* vol, const int64_t dims
         return LNF_EHIP;
     const uint32_t t = otsu_from_hist(h->otsu_host, levels);
     if (T) *T = t;
-    if (launch_rule(h->rule, vol, out, dtype, radius, g, t, ctx_tile(h, h->rule, dtype, radius, g),
-                    stream) != hipSuccess)
+    if (launch_rule(h->rule, h->geom, vol, out, dtype, radius, g, t,
+                    ctx_tile(h, h->rule, dtype, radius, g), stream) != hipSuccess)
         return LNF_EHIP;
     return LNF_OK;
 }

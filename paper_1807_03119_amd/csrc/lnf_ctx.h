@@ -24,6 +24,7 @@ struct lnf_ctx {
     int device = 0;
     int rule = LNF_MEAN9;
     uint32_t gate = 0;
+    uint32_t geom = 0;      // LNF_GEOM_* bits (0: cubes at offset r)
     mutable std::mutex mu;  // guards `tuned`
     std::unordered_map<lnf::TuneKey, lnf::TileCfg> tuned;
     void* dev_state = nullptr;  // library-internal device memory (see ctx_init_device_state)
@@ -51,7 +52,8 @@ int check_volume_args(const lnf_ctx* h, const void* vol, const int64_t dims[3], 
                       int radius, const void* out, Geom* g, size_t* bytes);
 int check_device_range(const void* p, size_t bytes, int device);
 TileCfg ctx_tile(const lnf_ctx* h, int rule, int dtype, int radius, Geom g);
-hipError_t launch_rule(int rule, const void* in, void* out, int dtype, int r, Geom g,
+hipError_t launch_rule(int rule, uint32_t geom, const void* in, void* out, int dtype, int r,
+                       Geom g,
                        uint32_t gate, TileCfg cfg, hipStream_t s);
 
 // Batch path (batch.hip).

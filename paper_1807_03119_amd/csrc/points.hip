@@ -131,6 +131,7 @@ extern "C" int lnf_filter_points(lnf_handle h, const void* vol, const int64_t di
                                  hipStream_t stream)
 {
     if (!h || !vol || !dims || n < 0 || (n > 0 && (!xyz || !out))) return LNF_EINVAL;
+    if (h->geom) return LNF_EINVAL;  // default cluster geometry only
     if (dtype != LNF_U8 && dtype != LNF_U16) return LNF_EINVAL;
     if (radius < 1 || radius > LNF_RADIUS_MAX) return LNF_EINVAL;
     for (int i = 0; i < 3; ++i)

@@ -68,14 +68,15 @@ extern "C" int lnf_tune(lnf_handle h, const lnf_job* sample, int n)
         for (int v = 0; v < nv && rc == LNF_OK; ++v) {
             for (int zs : zs_candidates(g.nz)) {
                 const TileCfg cfg{v, zs};
-                if (launch_rule(h->rule, j.in, j.out, j.dtype, j.radius, g, h->gate, cfg, s) !=
+                if (launch_rule(h->rule, h->geom, j.in, j.out, j.dtype, j.radius, g, h->gate, cfg, s) !=
                     hipSuccess) {
                     rc = LNF_EHIP;
                     break;
                 }
                 (void)hipEventRecord(e0, s);
                 for (int t = 0; t < kTimedRuns; ++t)
-                    (void)launch_rule(h->rule, j.in, j.out, j.dtype, j.radius, g, h->gate, cfg, s);
+                    (void)launch_rule(h->rule, h->geom, j.in, j.out, j.dtype, j.radius, g, h->gate, cfg,
+                                      s);
                 (void)hipEventRecord(e1, s);
                 float ms = 0.f;
                 if (hipEventSynchronize(e1) != hipSuccess ||

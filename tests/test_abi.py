@@ -62,7 +62,9 @@ def test_create_bad_options():
     assert lib.lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
     opt = _lib.lnf_options(4, 0, 0, -1, 0)
     assert lib.lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
-    for flags in (1, 2):  # reserved: must be 0
+    # unknown geometry bits, and the two offset bits together
+    for flags in (8, 0x80000000, _lib.LNF_GEOM_OFFSET_1 | _lib.LNF_GEOM_OFFSET_2R1,
+                  _lib.LNF_GEOM_CROSS | _lib.LNF_GEOM_OFFSET_1 | _lib.LNF_GEOM_OFFSET_2R1):
         opt = _lib.lnf_options(ctypes.sizeof(_lib.lnf_options), 0, 0, -1, flags)
         assert lib.lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
 

@@ -240,10 +240,10 @@ def test_extreme_values_every_variant(variant):
                 _assert_same(got, oracle.filter_volume(v, r), v, r, f"extremes v{variant} r={r}")
 
 
-def test_reserved_flags_rejected():
+def test_unknown_flags_rejected():
     import ctypes
     h = ctypes.c_void_p()
-    for flags in (1, 2, 0x80000000):
+    for flags in (8, 6, 0x80000000):
         opt = _lib.lnf_options(ctypes.sizeof(_lib.lnf_options), 0, 0, -1, flags)
         assert _lib.lib().lnf_create(ctypes.byref(h), ctypes.byref(opt)) == _lib.LNF_EINVAL
 
