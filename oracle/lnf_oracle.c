@@ -263,3 +263,89 @@ int lnfo_threads(void)
     }
     return t;
 }
+
+/* ---- comparison filters (paper, Section "Other Filters") -------------------
+ * TEST INFRASTRUCTURE ONLY, like everything in this file.  Readings where the
+ * paper's formulas are garbled or silent (each filter starts from the same
+ * clamped sampling as above; averages round half up, exactly):
+ *   mean    (eq. 4)  mean of the (2r+1)^3 cube about the voxel;
+ *   sigma   (eq. 5)  mean of the cube's values v with |v - P0| <= w, P0 the
+ *                    centre value, w the half width of the accepted range (the
+ *                    paper's 2 sigma; the caller passes it);
+ *   Okada   (eq. 6)  mean of the centre and its six face neighbours whose
+ *                    difference to the centre is below t_d (strictly); 0 when
+ *                    none is (t_d = 0);
+ *   entropy (eq. 7)  P0 when the sum over the cube of -p log2 p (p the global
+ *                    frequency of each voxel's grey level, in fixed point:
+ *                    weights[level] in units of 2^-32) exceeds te_fixed, else 0.
+ * The gate (out < gate_T -> 0) applies to every output, as to the main filter. */
+#define LNFO_CMP_MEAN 0
+#define LNFO_CMP_SIGMA 1
+#define LNFO_CMP_OKADA 2
+#define LNFO_CMP_ENTROPY 3
+
+static uint32_t compare_voxel(const grid_t* g, int kind, int r, int64_t param,
+                              const int64_t* weights, uint32_t gate_T, int64_t px, int64_t py,
+                              int64_t pz)
+{
+    const uint64_t p0 = sample(g, px, py, pz);
+    uint64_t out = 0;
+    if (kind == LNFO_CMP_OKADA) {
+        static const int nb[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0},
+                                     {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+        uint64_t sum = 0, cnt = 0;
+        for (int i = 0; i < 7; ++i) {
+            uint64_t v = sample(g, px + nb[i][0], py + nb[i][1], pz + nb[i][2]);
+            uint64_t diff = v > p0 ? v - p0 : p0 - v;
+            if ((int64_t)diff < param) {
+                sum += v;
+                cnt += 1;
+            }
+        }
+        out = cnt ? (2 * sum + cnt) / (2 * cnt) : 0;
+    } else {
+        uint64_t sum = 0, cnt = 0;
+        int64_t h = 0;
+        for (int64_t az = -r; az <= r; ++az)
+            for (int64_t ay = -r; ay <= r; ++ay)
+                for (int64_t ax = -r; ax <= r; ++ax) {
+                    uint64_t v = sample(g, px + ax, py + ay, pz + az);
+                    if (kind == LNFO_CMP_ENTROPY) {
+                        h += weights[v];
+                    } else {
+                        uint64_t diff = v > p0 ? v - p0 : p0 - v;
+                        if (kind == LNFO_CMP_MEAN || (int64_t)diff <= param) {
+                            sum += v;
+                            cnt += 1;
+                        }
+                    }
+                }
+        if (kind == LNFO_CMP_ENTROPY) out = h > param ? p0 : 0;
+        else out = (2 * sum + cnt) / (2 * cnt);
+    }
+    if (out < gate_T) out = 0;
+    return (uint32_t)out;
+}
+
+/* Whole-volume comparison filter; param: sigma half width, Okada t_d, or the
+ * entropy threshold in 2^-32 units; weights: entropy only (levels entries). */
+int lnfo_compare(const void* vol, int64_t nx, int64_t ny, int64_t nz, int dtype, int kind,
+                 int r, int64_t param, const int64_t* weights, uint32_t gate_T, void* out)
+{
+    if (check_args(vol, nx, ny, nz, dtype, r, LNFO_MEAN9) || !out) return -1;
+    if (kind < LNFO_CMP_MEAN || kind > LNFO_CMP_ENTROPY) return -1;
+    if (kind == LNFO_CMP_ENTROPY && !weights) return -1;
+    grid_t g = {vol, nx, ny, nz, dtype};
+    int64_t plane = nx * ny;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t zy = 0; zy < nz * ny; ++zy) {
+        int64_t z = zy / ny, y = zy % ny;
+        for (int64_t x = 0; x < nx; ++x) {
+            uint32_t v = compare_voxel(&g, kind, r, param, weights, gate_T, x, y, z);
+            int64_t idx = z * plane + y * nx + x;
+            if (dtype == 1) ((uint8_t*)out)[idx] = (uint8_t)v;
+            else ((uint16_t*)out)[idx] = (uint16_t)v;
+        }
+    }
+    return 0;
+}
