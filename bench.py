@@ -313,6 +313,19 @@ def main():
                     ms2, _ = time_launches(lambda: g(vol, r, out=out), 5, 1, stream)
                     extras[f"geom_{gname}_{rule_name}_r{r}_Gvox_s"] = nvox / (ms2 * 1e-3) / 1e9
                 g.close()
+        log("timing the paper's comparison filters at M = 3 (r = 1)")
+        g = Filter(_lib.LNF_MEAN9, 0)
+        _, hw = g.sigma(vol, 1, -1, out=out)  # floor(2 sigma) of the phantom, once
+        cmp = {"ours_mean9": lambda: g(vol, 1, out=out),
+               "mean": lambda: g.mean(vol, 1, out=out),
+               "sigma": lambda: g.sigma(vol, 1, hw, out=out),
+               "okada": lambda: g.okada(vol, 64, out=out),
+               "entropy_incl_histogram": lambda: g.entropy(vol, 1, 2.0, out=out)}
+        for name, fn in cmp.items():
+            ms2, _ = time_launches(fn, 5, 1, stream)
+            extras[f"compare_r1_{name}_ms"] = ms2
+        extras["compare_r1_sigma_half_width"] = hw
+        g.close()
         log("timing the 64-volume mixed batch")
         extras["batch64"] = batch_benchmark(rule_code, stream)
         res["extras"] = extras

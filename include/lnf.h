@@ -210,6 +210,45 @@ LNF_API int lnf_otsu_threshold(const uint64_t* hist, int levels, uint32_t* T);
 LNF_API int lnf_filter_otsu(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
                             int radius, void* out, hipStream_t stream, uint32_t* T);
 
+/* ---- comparison filters (paper, Section "Other Filters") ----------------- */
+/*
+ * The four spatially variant filters the paper compares its method with, as
+ * it adapts them to 3D.  Each samples like lnf_filter (coordinates clamped
+ * into the volume), rounds averages half up in exact arithmetic, writes the
+ * input dtype, and applies the context's gate (out < gate_T -> 0).  The
+ * context's rule and geometry are not used.  Readings of the paper's garbled
+ * or silent formulas:
+ *   mean (eq. 4)     rounded mean of the (2r+1)^3 cube about the voxel;
+ *   sigma (eq. 5)    rounded mean of the cube's values v with |v - P0| <= w (P0
+ *                    the centre value): the paper's 2-sigma range with
+ *                    w = half_width, or, for half_width < 0, w = floor(2 sigma)
+ *                    with sigma the standard deviation of all voxel values
+ *                    (computed exactly from a histogram; volumes below 2^32
+ *                    voxels); *used_half_width (if not NULL) receives w;
+ *   Okada (eq. 6)    rounded mean of the centre and its six face neighbours
+ *                    whose difference to the centre is < t_d; 0 if none is
+ *                    (t_d = 0);
+ *   entropy (eq. 7)  P0 if H > t_e, else 0, where H sums -p log2 p over the
+ *                    cube's voxels, p the frequency of the voxel's grey level
+ *                    in the whole volume; weights and threshold in 2^-32 fixed
+ *                    point (floor(x * 2^32 + 1/2), x in fp64 with the C
+ *                    library's log2).
+ * lnf_filter_mean and lnf_filter_okada are asynchronous on `stream`;
+ * lnf_filter_sigma with half_width < 0 and lnf_filter_entropy read a
+ * histogram back first (they synchronise `stream`).  Radius 1..LNF_RADIUS_MAX
+ * (Okada: the six face neighbours only).
+ * Errors: as lnf_filter; LNF_EINVAL also for a non-finite t_e; LNF_ENOMEM.
+ */
+LNF_API int lnf_filter_mean(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                            int radius, void* out, hipStream_t stream);
+LNF_API int lnf_filter_sigma(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                             int radius, int64_t half_width, void* out, hipStream_t stream,
+                             int64_t* used_half_width);
+LNF_API int lnf_filter_okada(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                             uint32_t t_d, void* out, hipStream_t stream);
+LNF_API int lnf_filter_entropy(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                               int radius, double t_e, void* out, hipStream_t stream);
+
 /* ---- surface-point mode ------------------------------------------------ */
 /*
  * The filter evaluated only at listed voxels, as the paper applies it at the

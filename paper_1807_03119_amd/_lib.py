@@ -98,6 +98,13 @@ def _declare(lib):
         "lnf_otsu_threshold": [_vp, _i32, ctypes.POINTER(ctypes.c_uint32)],
         "lnf_filter_otsu": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, _vp, _vp,
                             ctypes.POINTER(ctypes.c_uint32)],
+        "lnf_filter_mean": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, _vp, _vp],
+        "lnf_filter_sigma": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32,
+                             ctypes.c_int64, _vp, _vp, ctypes.POINTER(ctypes.c_int64)],
+        "lnf_filter_okada": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, ctypes.c_uint32,
+                             _vp, _vp],
+        "lnf_filter_entropy": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32,
+                               ctypes.c_double, _vp, _vp],
     }
     _u64, _i64 = ctypes.c_uint64, ctypes.c_int64
     sig.update({
@@ -368,6 +375,33 @@ def lnf_filter_otsu(h, vol, dims, dtype: int, radius: int, out, stream=None):
     rc = lib().lnf_filter_otsu(h, vp, _dims_t(*[int(v) for v in dims]), dtype, radius, op,
                                stream_ptr(stream), ctypes.byref(t))
     return rc, t.value
+
+
+def _p(t):
+    return t if isinstance(t, int) else t.data_ptr()
+
+
+def lnf_filter_mean(h, vol, dims, dtype: int, radius: int, out, stream=None) -> int:
+    return lib().lnf_filter_mean(h, _p(vol), _dims_t(*[int(v) for v in dims]), dtype, radius,
+                                 _p(out), stream_ptr(stream))
+
+
+def lnf_filter_sigma(h, vol, dims, dtype: int, radius: int, half_width: int, out, stream=None):
+    """Returns (rc, half width used)."""
+    w = ctypes.c_int64()
+    rc = lib().lnf_filter_sigma(h, _p(vol), _dims_t(*[int(v) for v in dims]), dtype, radius,
+                                int(half_width), _p(out), stream_ptr(stream), ctypes.byref(w))
+    return rc, w.value
+
+
+def lnf_filter_okada(h, vol, dims, dtype: int, t_d: int, out, stream=None) -> int:
+    return lib().lnf_filter_okada(h, _p(vol), _dims_t(*[int(v) for v in dims]), dtype, int(t_d),
+                                  _p(out), stream_ptr(stream))
+
+
+def lnf_filter_entropy(h, vol, dims, dtype: int, radius: int, t_e: float, out, stream=None) -> int:
+    return lib().lnf_filter_entropy(h, _p(vol), _dims_t(*[int(v) for v in dims]), dtype, radius,
+                                    float(t_e), _p(out), stream_ptr(stream))
 
 
 def lnf_filter_points(h, vol, dims, dtype: int, radius: int, xyz, n: int, out, stream=None) -> int:

@@ -60,6 +60,37 @@ class Filter:
             raise LnfError(rc, "lnf_filter_otsu")
         return out, t
 
+    # ---- the paper's comparison filters (context gate applies; rule unused) ----
+    def _compare(self, name, fn, vol, out, *args):
+        import torch
+        _require_cuda(vol, "vol")
+        if out is None:
+            out = torch.empty_like(vol)
+        res = fn(self._h, vol, _lib.dims_of(vol), _lib.dtype_code(vol), *args[:-1], out, args[-1])
+        rc = res[0] if isinstance(res, tuple) else res
+        if rc != _lib.LNF_OK:
+            raise LnfError(rc, name)
+        return (out, res[1]) if isinstance(res, tuple) else out
+
+    def mean(self, vol, radius: int, out=None, stream=None):
+        """The paper's mean filter (eq. 4)."""
+        return self._compare("lnf_filter_mean", _lib.lnf_filter_mean, vol, out, int(radius), stream)
+
+    def sigma(self, vol, radius: int, half_width: int = -1, out=None, stream=None):
+        """Sigma filter (eq. 5); half_width < 0: floor(2 sigma) of the volume.
+        Returns (out, half width used)."""
+        return self._compare("lnf_filter_sigma", _lib.lnf_filter_sigma, vol, out, int(radius),
+                             int(half_width), stream)
+
+    def okada(self, vol, t_d: int, out=None, stream=None):
+        """Okada filter (eq. 6) over the six face neighbours."""
+        return self._compare("lnf_filter_okada", _lib.lnf_filter_okada, vol, out, int(t_d), stream)
+
+    def entropy(self, vol, radius: int, t_e: float, out=None, stream=None):
+        """Entropy filter (eq. 7)."""
+        return self._compare("lnf_filter_entropy", _lib.lnf_filter_entropy, vol, out, int(radius),
+                             float(t_e), stream)
+
     def points(self, vol, radius: int, xyz, stream=None):
         """Filtered values at voxels xyz (int32 [n, 3] device tensor of (x, y, z))."""
         import torch

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblnf.so")
 
-SOURCES = ["api.cpp", "mean9.hip", "minvar9.hip", "batch.hip", "tune.cpp", "server.cpp", "histogram.hip", "points.hip", "cluster.hip"]
+SOURCES = ["api.cpp", "mean9.hip", "minvar9.hip", "batch.hip", "tune.cpp", "server.cpp", "histogram.hip", "points.hip", "cluster.hip", "window.hip"]
 
 ARCH = "gfx950"
 CFLAGS = [

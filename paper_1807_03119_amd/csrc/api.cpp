@@ -159,6 +159,7 @@ void ctx_free_device_state(lnf_ctx* c)
 {
     batch_state_free(c);
     otsu_scratch_free(c);
+    entropy_scratch_free(c);
     c->dev_state = nullptr;
 }
 

@@ -10,12 +10,13 @@
 namespace lnf {
 namespace {
 
-template <int R, int D, int SHAPE, bool VAR, typename T>
+template <int R, int D, int SHAPE, int RULE, typename T>
 __global__ __launch_bounds__(256) void cluster_planes(const T* __restrict__ in,
                                                       T* __restrict__ out, Geom g, int zs,
                                                       int tiles_x, int tiles_y, int total,
                                                       uint32_t gate)
 {
+    constexpr bool VAR = RULE == kRuleMinVar9;
     using S = CTShape<R, D, SHAPE, VAR>;
     __shared__ __align__(16) CTSmem<R, D, SHAPE, VAR> sm;
     const int tile = xcd_tile(blockIdx.x, total);
@@ -24,15 +25,15 @@ __global__ __launch_bounds__(256) void cluster_planes(const T* __restrict__ in,
     const int by = rest % tiles_y;
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
-    cluster_tile<R, D, SHAPE, VAR, T>(sm, in, out, g, bx * S::TX, by * S::TY, z0,
-                                      min(z0 + zs, g.nz), gate);
+    cluster_tile<R, D, SHAPE, RULE, T>(sm, in, out, g, bx * S::TX, by * S::TY, z0,
+                                       min(z0 + zs, g.nz), gate);
 }
 
-template <int R, int D, int SHAPE, bool VAR, typename T>
+template <int R, int D, int SHAPE, int RULE, typename T>
 hipError_t launch_geom(const void* in, void* out, Geom g, uint32_t gate, int zs, hipStream_t s)
 {
-    using S = CTShape<R, D, SHAPE, VAR>;
-    const auto kern = cluster_planes<R, D, SHAPE, VAR, T>;
+    using S = CTShape<R, D, SHAPE, RULE == kRuleMinVar9>;
+    const auto kern = cluster_planes<R, D, SHAPE, RULE, T>;
     const int tiles_x = (g.nx + S::TX - 1) / S::TX, tiles_y = (g.ny + S::TY - 1) / S::TY;
     if (zs <= 0)
         zs = default_zs(tiles_x * tiles_y, g.nz, resident_groups((const void*)kern, 256));
@@ -43,15 +44,15 @@ hipError_t launch_geom(const void* in, void* out, Geom g, uint32_t gate, int zs,
     return hipGetLastError();
 }
 
-template <int R, int SHAPE, bool VAR, typename T>
+template <int R, int SHAPE, int RULE, typename T>
 hipError_t launch_offset(int offset, const void* in, void* out, Geom g, uint32_t gate, int zs,
                          hipStream_t s)
 {
     switch (offset) {
-    case LNF_GEOM_OFFSET_1: return launch_geom<R, 1, SHAPE, VAR, T>(in, out, g, gate, zs, s);
+    case LNF_GEOM_OFFSET_1: return launch_geom<R, 1, SHAPE, RULE, T>(in, out, g, gate, zs, s);
     case LNF_GEOM_OFFSET_2R1:
-        return launch_geom<R, 2 * R + 1, SHAPE, VAR, T>(in, out, g, gate, zs, s);
-    default: return launch_geom<R, R, SHAPE, VAR, T>(in, out, g, gate, zs, s);
+        return launch_geom<R, 2 * R + 1, SHAPE, RULE, T>(in, out, g, gate, zs, s);
+    default: return launch_geom<R, R, SHAPE, RULE, T>(in, out, g, gate, zs, s);
     }
 }
 
@@ -63,11 +64,23 @@ hipError_t launch_r(int rule, uint32_t geom, const void* in, void* out, Geom g, 
     const bool var = rule == LNF_MINVAR9;
     if (geom & LNF_GEOM_CROSS) {
         if (var)
-            return launch_offset<R, kClusterCross, true, T>(offset, in, out, g, gate, zs, s);
-        return launch_offset<R, kClusterCross, false, T>(offset, in, out, g, gate, zs, s);
+            return launch_offset<R, kClusterCross, kRuleMinVar9, T>(offset, in, out, g, gate, zs, s);
+        return launch_offset<R, kClusterCross, kRuleMean9, T>(offset, in, out, g, gate, zs, s);
     }
-    if (var) return launch_offset<R, kClusterBox, true, T>(offset, in, out, g, gate, zs, s);
-    return launch_offset<R, kClusterBox, false, T>(offset, in, out, g, gate, zs, s);
+    if (var) return launch_offset<R, kClusterBox, kRuleMinVar9, T>(offset, in, out, g, gate, zs, s);
+    return launch_offset<R, kClusterBox, kRuleMean9, T>(offset, in, out, g, gate, zs, s);
+}
+
+template <typename T>
+hipError_t dispatch_mean(int r, const void* in, void* out, Geom g, uint32_t gate, hipStream_t s)
+{
+    switch (r) {
+    case 1: return launch_geom<1, 0, kClusterBox, kRuleBoxMean, T>(in, out, g, gate, 0, s);
+    case 2: return launch_geom<2, 0, kClusterBox, kRuleBoxMean, T>(in, out, g, gate, 0, s);
+    case 3: return launch_geom<3, 0, kClusterBox, kRuleBoxMean, T>(in, out, g, gate, 0, s);
+    case 4: return launch_geom<4, 0, kClusterBox, kRuleBoxMean, T>(in, out, g, gate, 0, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T>
@@ -84,6 +97,13 @@ hipError_t dispatch(int rule, uint32_t geom, int r, const void* in, void* out, G
 }
 
 }  // namespace
+
+hipError_t launch_box_mean(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
+                           hipStream_t s)
+{
+    if (dtype == LNF_U8) return dispatch_mean<uint8_t>(r, in, out, g, gate, s);
+    return dispatch_mean<uint16_t>(r, in, out, g, gate, s);
+}
 
 hipError_t launch_geometry(int rule, uint32_t geom, const void* in, void* out, int dtype, int r,
                            Geom g, uint32_t gate, int zs, hipStream_t s)

@@ -24,6 +24,9 @@
 namespace lnf {
 
 constexpr int kClusterBox = 0, kClusterCross = 1;
+// rules of the tile: the two nine-cluster rules, and the plain box mean (the
+// paper's mean filter, eq. 4: with D = 0 the "gather" is the centre cluster)
+constexpr int kRuleMean9 = 0, kRuleMinVar9 = 1, kRuleBoxMean = 2;
 
 template <int R, int D, bool VAR>
 struct CTDims {
@@ -73,7 +76,7 @@ struct CTSmem {
     uint32_t gs[S::NP][S::NCOL];
 };
 
-template <int R, int D, int SHAPE, bool VAR, typename T>
+template <int R, int D, int SHAPE, int RULE, typename T, bool VAR = RULE == kRuleMinVar9>
 __device__ __forceinline__ void cluster_tile(CTSmem<R, D, SHAPE, VAR>& sm,
                                              const T* __restrict__ in, T* __restrict__ out,
                                              Geom g, int x0, int y0, int z0, int z1,
@@ -235,7 +238,9 @@ __device__ __forceinline__ void cluster_tile(CTSmem<R, D, SHAPE, VAR>& sm,
                 const int sm1 = (k - R - 2 * D + 4 * NP) % NP;  // plane z - D
                 const int sp1 = slot;                           // plane z + D
                 uint32_t o;
-                if constexpr (!VAR) {
+                if constexpr (RULE == kRuleBoxMean) {
+                    o = round_div_odd(sm.gs[s0][(oy + D) * GX + ox + D], invn);
+                } else if constexpr (!VAR) {
                     uint32_t tot = sm.gs[s0][(oy + D) * GX + ox + D];
 #pragma unroll
                     for (int kk = 1; kk < 9; ++kk) {

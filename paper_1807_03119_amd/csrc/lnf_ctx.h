@@ -32,6 +32,7 @@ struct lnf_ctx {
     std::mutex otsu_mu;                 // guards the Otsu scratch below
     uint64_t* otsu_dev = nullptr;       // 65536 histogram counters (lnf_filter_otsu)
     uint64_t* otsu_host = nullptr;      // pinned copy read by the host
+    int64_t* entropy_dev = nullptr;     // 65536 fixed-point level weights (lnf_filter_entropy)
 };
 
 namespace lnf {
@@ -60,6 +61,9 @@ hipError_t launch_rule(int rule, uint32_t geom, const void* in, void* out, int d
 int validate_jobs(const lnf_ctx* h, const lnf_job* jobs, int n, std::vector<Geom>* geoms);
 void batch_state_free(lnf_ctx* h);
 void otsu_scratch_free(lnf_ctx* h);
+void entropy_scratch_free(lnf_ctx* h);
+// Histogram of n voxels into hist (cleared first), asynchronous on s (histogram.hip).
+hipError_t launch_histogram(const void* vol, size_t n, int dtype, uint64_t* hist, hipStream_t s);
 
 // Allocate / release the context's internal device memory.
 int ctx_init_device_state(lnf_ctx* c);

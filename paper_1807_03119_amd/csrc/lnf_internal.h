@@ -40,6 +40,13 @@ inline bool mean9_pairs_ok(const void* base, int nx, size_t elem)
 // ---- geometry variants (cluster_tile.h): LNF_GEOM_* bits, both rules -------
 hipError_t launch_geometry(int rule, uint32_t geom, const void* in, void* out, int dtype, int r,
                            Geom g, uint32_t gate, int zs, hipStream_t s);
+// The paper's mean filter (eq. 4): rounded mean of the (2r+1)^3 cube, gated.
+hipError_t launch_box_mean(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
+                           hipStream_t s);
+// Sigma / Okada / entropy comparison filters (window.hip).
+constexpr int kWinSigma = 0, kWinOkada = 1, kWinEntropy = 2;
+hipError_t launch_window(int kind, const void* in, void* out, int dtype, int r, Geom g,
+                         int64_t param, const int64_t* weights, uint32_t gate, hipStream_t s);
 
 // ---- MINVAR9 (least-variance cluster) -------------------------------------
 int minvar9_variants();
