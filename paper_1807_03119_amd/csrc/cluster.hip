@@ -72,18 +72,6 @@ hipError_t launch_r(int rule, uint32_t geom, const void* in, void* out, Geom g, 
 }
 
 template <typename T>
-hipError_t dispatch_mean(int r, const void* in, void* out, Geom g, uint32_t gate, hipStream_t s)
-{
-    switch (r) {
-    case 1: return launch_geom<1, 0, kClusterBox, kRuleBoxMean, T>(in, out, g, gate, 0, s);
-    case 2: return launch_geom<2, 0, kClusterBox, kRuleBoxMean, T>(in, out, g, gate, 0, s);
-    case 3: return launch_geom<3, 0, kClusterBox, kRuleBoxMean, T>(in, out, g, gate, 0, s);
-    case 4: return launch_geom<4, 0, kClusterBox, kRuleBoxMean, T>(in, out, g, gate, 0, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename T>
 hipError_t dispatch(int rule, uint32_t geom, int r, const void* in, void* out, Geom g,
                     uint32_t gate, int zs, hipStream_t s)
 {
@@ -97,13 +85,6 @@ hipError_t dispatch(int rule, uint32_t geom, int r, const void* in, void* out, G
 }
 
 }  // namespace
-
-hipError_t launch_box_mean(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
-                           hipStream_t s)
-{
-    if (dtype == LNF_U8) return dispatch_mean<uint8_t>(r, in, out, g, gate, s);
-    return dispatch_mean<uint16_t>(r, in, out, g, gate, s);
-}
 
 hipError_t launch_geometry(int rule, uint32_t geom, const void* in, void* out, int dtype, int r,
                            Geom g, uint32_t gate, int zs, hipStream_t s)

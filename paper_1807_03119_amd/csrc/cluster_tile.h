@@ -24,9 +24,8 @@
 namespace lnf {
 
 constexpr int kClusterBox = 0, kClusterCross = 1;
-// rules of the tile: the two nine-cluster rules, and the plain box mean (the
-// paper's mean filter, eq. 4: with D = 0 the "gather" is the centre cluster)
-constexpr int kRuleMean9 = 0, kRuleMinVar9 = 1, kRuleBoxMean = 2;
+// rules of the tile
+constexpr int kRuleMean9 = 0, kRuleMinVar9 = 1;
 
 template <int R, int D, bool VAR>
 struct CTDims {
@@ -238,9 +237,7 @@ __device__ __forceinline__ void cluster_tile(CTSmem<R, D, SHAPE, VAR>& sm,
                 const int sm1 = (k - R - 2 * D + 4 * NP) % NP;  // plane z - D
                 const int sp1 = slot;                           // plane z + D
                 uint32_t o;
-                if constexpr (RULE == kRuleBoxMean) {
-                    o = round_div_odd(sm.gs[s0][(oy + D) * GX + ox + D], invn);
-                } else if constexpr (!VAR) {
+                if constexpr (!VAR) {
                     uint32_t tot = sm.gs[s0][(oy + D) * GX + ox + D];
 #pragma unroll
                     for (int kk = 1; kk < 9; ++kk) {

@@ -201,6 +201,53 @@ __global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS)) void mean9_stream(
                                     min(z0 + zs, g.nz), gate, inv9n);
 }
 
+// The paper's mean filter (eq. 4): the box term of the same streaming tile,
+// 64 x 16 tiles.
+template <int R, typename T, bool GATE>
+__global__ __launch_bounds__((M9Shape<R, 16, 64>::THREADS)) void box_mean_stream(
+    const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
+    int total, uint32_t gate, double invn, int pairs)
+{
+    __shared__ __align__(16) M9SmemAny<R, 16, 64, true> sm;
+    const int tile = xcd_tile(blockIdx.x, total);
+    const int bx = tile % tiles_x;
+    const int rest = tile / tiles_x;
+    const int by = rest % tiles_y;
+    const int bz = rest / tiles_y;
+    const int z0 = bz * zs;
+    mean9_tile<R, 16, T, GATE, 64, true>(sm, pairs != 0, in, out, g, bx * 64, by * 16, z0,
+                                         min(z0 + zs, g.nz), gate, invn);
+}
+
+template <int R, typename T, bool GATE>
+hipError_t launch_box(const T* in, T* out, Geom g, uint32_t gate, hipStream_t s)
+{
+    constexpr int threads = M9Shape<R, 16, 64>::THREADS;
+    const auto kern = box_mean_stream<R, T, GATE>;
+    const int tiles_x = (g.nx + 63) / 64, tiles_y = (g.ny + 15) / 16;
+    const int zs = default_zs(tiles_x * tiles_y, g.nz, resident_groups((const void*)kern, threads));
+    const int total = tiles_x * tiles_y * ((g.nz + zs - 1) / zs);
+    const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
+    const int pairs = mean9_pairs_ok(in, g.nx, sizeof(T)) ? 1 : 0;
+    hipLaunchKernelGGL(kern, dim3(total), dim3(threads), 0, s, in, out, g, zs, tiles_x, tiles_y,
+                       total, gate, 1.0 / n, pairs);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_box(int r, const void* in, void* out, Geom g, uint32_t gate, hipStream_t s)
+{
+    const T* pin = static_cast<const T*>(in);
+    T* pout = static_cast<T*>(out);
+    switch (r) {
+    case 1: return gate ? launch_box<1, T, true>(pin, pout, g, gate, s) : launch_box<1, T, false>(pin, pout, g, gate, s);
+    case 2: return gate ? launch_box<2, T, true>(pin, pout, g, gate, s) : launch_box<2, T, false>(pin, pout, g, gate, s);
+    case 3: return gate ? launch_box<3, T, true>(pin, pout, g, gate, s) : launch_box<3, T, false>(pin, pout, g, gate, s);
+    case 4: return gate ? launch_box<4, T, true>(pin, pout, g, gate, s) : launch_box<4, T, false>(pin, pout, g, gate, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 struct Variant {
     int tx, ty, threads;
 };
@@ -296,6 +343,13 @@ void mean9_tile_shape(int variant, int* tx, int* ty)
     const Variant v = kVariants[(variant >= 0 && variant < kNumVariants) ? variant : 1];
     *tx = v.tx;
     *ty = v.ty;
+}
+
+hipError_t launch_box_mean(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
+                           hipStream_t s)
+{
+    if (dtype == LNF_U8) return dispatch_box<uint8_t>(r, in, out, g, gate, s);
+    return dispatch_box<uint16_t>(r, in, out, g, gate, s);
 }
 
 hipError_t launch_mean9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,

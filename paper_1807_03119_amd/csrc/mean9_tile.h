@@ -82,16 +82,18 @@ struct M9Shape {
     static_assert(SWW % 2 == 0 && LXE % 2 == 0, "x-pass reads whole 8-byte pieces");
 };
 
-template <int R, int TY, int TXW = 64, bool PK = false>
+// BOX: the box term alone (the paper's mean filter, eq. 4): no qx, no Q ring.
+template <int R, int TY, int TXW = 64, bool PK = false, bool BOX = false>
 struct M9Smem {
     using S = M9Shape<R, TY, TXW, PK>;
     uint32_t raw[S::NRB][S::NLOAD * S::THREADS];
     uint32_t px[2][S::LY * S::PXP];
-    uint32_t qx[2][S::LY * S::PXP];
+    uint32_t qx[BOX ? 1 : 2][BOX ? 1 : S::LY * S::PXP];
 };
 
-template <int R, int TY, typename T, bool GATE, int TXW, bool PK>
-__device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK>& sm,
+// inv_div: 1/(9n), or 1/n with BOX.
+template <int R, int TY, typename T, bool GATE, int TXW, bool PK, bool BOX = false>
+__device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK, BOX>& sm,
                                                 const T* __restrict__ in, T* __restrict__ out,
                                                 Geom g, int x0, int y0, int z0, int z1,
                                                 uint32_t gate, double inv9n)
@@ -169,15 +171,18 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK>& sm,
         for (int i = 1; i < S::SW; ++i) c[i] = c[i - 1] + el(i);
 #pragma unroll
         for (int m = 0; m < S::SEG; ++m) {
-            qq[m] = c[m + 4 * R] - (m ? c[m - 1] : 0u) + el(m + 2 * R);
+            if constexpr (!BOX) qq[m] = c[m + 4 * R] - (m ? c[m - 1] : 0u) + el(m + 2 * R);
             pp[m] = c[m + 3 * R] - c[m + R - 1];
         }
         uint32_t* pd = sm.px[buf] + xrow * PXP + xseg * S::SEG;
-        uint32_t* qd = sm.qx[buf] + xrow * PXP + xseg * S::SEG;
 #pragma unroll
         for (int m = 0; m < S::SEG; m += 4) {
             *reinterpret_cast<uint4*>(pd + m) = make_uint4(pp[m], pp[m + 1], pp[m + 2], pp[m + 3]);
-            *reinterpret_cast<uint4*>(qd + m) = make_uint4(qq[m], qq[m + 1], qq[m + 2], qq[m + 3]);
+            if constexpr (!BOX) {
+                uint32_t* qd = sm.qx[buf] + xrow * PXP + xseg * S::SEG;
+                *reinterpret_cast<uint4*>(qd + m) =
+                    make_uint4(qq[m], qq[m + 1], qq[m + 2], qq[m + 3]);
+            }
         }
     };
     auto xpass = [&](int buf) {
@@ -190,7 +195,8 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK>& sm,
 
     // Value of px (Q = false) or qx (Q = true) at x-pass row `row`, column xq.
     auto xval = [&](int pb, bool q, int row) -> uint32_t {
-        return (q ? sm.qx[pb] : sm.px[pb])[row * PXP + xq];
+        if constexpr (BOX) return sm.px[pb][row * PXP + xq];
+        else return (q ? sm.qx[pb] : sm.px[pb])[row * PXP + xq];
     };
 
     // y-pass / ring ownership: column xq, rows yg*YO .. yg*YO+YO-1
@@ -221,7 +227,7 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK>& sm,
     // the compiler can interleave.
     for (int i = tid; i < S::LY * PXP; i += S::THREADS) {
         sm.px[1][i] = 0;
-        sm.qx[1][i] = 0;
+        if constexpr (!BOX) sm.qx[1][i] = 0;
     }
     const int ns = (z1 - z0) + 2 * H;  // input slices z0-2r .. z1-1+2r
     // the YO stores of output slice zo; zo < 0 stores to an empty buffer
@@ -256,8 +262,10 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK>& sm,
             uint32_t pv[S::NPV], qv[S::NQV];
 #pragma unroll
             for (int i = 0; i < S::NPV; ++i) pv[i] = xval(pb, false, yg * YO + R + i);
+            if constexpr (!BOX) {
 #pragma unroll
-            for (int i = 0; i < S::NQV; ++i) qv[i] = xval(pb, true, yg * YO + i);
+                for (int i = 0; i < S::NQV; ++i) qv[i] = xval(pb, true, yg * YO + i);
+            }
             {
                 // z-window of slice j = k-2, whose P and Q entered the ring in
                 // the previous iteration; it reads slot j+1 (Q of slice j-4r-1)
@@ -267,9 +275,13 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK>& sm,
 #pragma unroll
                 for (int m = 0; m < YO; ++m) {
                     bacc[m] += pr[(uj + D - R) % D][m] - pr[(uj + R + 1) % D][m];
-                    wacc[m] += qr[uj][m] - qr[(uj + 1) % D][m];
-                    const uint32_t Ssum = bacc[m] + wacc[m] + qr[(uj + D - 2 * R) % D][m];
-                    o[m] = round_div_odd(Ssum, inv9n);
+                    if constexpr (BOX) {
+                        o[m] = round_div_odd(bacc[m], inv9n);
+                    } else {
+                        wacc[m] += qr[uj][m] - qr[(uj + 1) % D][m];
+                        const uint32_t Ssum = bacc[m] + wacc[m] + qr[(uj + D - 2 * R) % D][m];
+                        o[m] = round_div_odd(Ssum, inv9n);
+                    }
                     if (GATE && o[m] < gate) o[m] = 0;
                 }
                 store_out((k - 2 >= 2 * H) ? z0 + k - 2 - 2 * H : -1, o);
@@ -279,15 +291,17 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK>& sm,
                 const int uy = (u + D - 1) % D;
                 uint32_t cp[S::NPV], cq[S::NQV];
                 cp[0] = pv[0];
-                cq[0] = qv[0];
 #pragma unroll
                 for (int i = 1; i < S::NPV; ++i) cp[i] = cp[i - 1] + pv[i];
 #pragma unroll
-                for (int i = 1; i < S::NQV; ++i) cq[i] = cq[i - 1] + qv[i];
+                for (int m = 0; m < YO; ++m) pr[uy][m] = cp[m + 2 * R] - (m ? cp[m - 1] : 0u);
+                if constexpr (!BOX) {
+                    cq[0] = qv[0];
 #pragma unroll
-                for (int m = 0; m < YO; ++m) {
-                    pr[uy][m] = cp[m + 2 * R] - (m ? cp[m - 1] : 0u);
-                    qr[uy][m] = cq[m + 4 * R] - (m ? cq[m - 1] : 0u) + qv[m + 2 * R];
+                    for (int i = 1; i < S::NQV; ++i) cq[i] = cq[i - 1] + qv[i];
+#pragma unroll
+                    for (int m = 0; m < YO; ++m)
+                        qr[uy][m] = cq[m + 4 * R] - (m ? cq[m - 1] : 0u) + qv[m + 2 * R];
                 }
             }
             // slice i lives in raw slot i mod NRB: slice k+PF takes the slot
@@ -304,26 +318,27 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK>& sm,
 }
 
 // LDS for either staging; a kernel that may run both holds the union.
-template <int R, int TY, int TXW = 64>
+template <int R, int TY, int TXW = 64, bool BOX = false>
 union M9SmemAny {
-    M9Smem<R, TY, TXW, false> e;  // element-wise staging
-    M9Smem<R, TY, TXW, true> p;   // paired staging
+    M9Smem<R, TY, TXW, false, BOX> e;  // element-wise staging
+    M9Smem<R, TY, TXW, true, BOX> p;   // paired staging
 };
 
 // One tile; `pairs` (mean9_pairs_ok for the volume) selects paired staging
 // for the tiles whose x halo stays inside the volume.
-template <int R, int TY, typename T, bool GATE, int TXW = 64>
-__device__ __forceinline__ void mean9_tile(M9SmemAny<R, TY, TXW>& sm, bool pairs,
+template <int R, int TY, typename T, bool GATE, int TXW = 64, bool BOX = false>
+__device__ __forceinline__ void mean9_tile(M9SmemAny<R, TY, TXW, BOX>& sm, bool pairs,
                                            const T* __restrict__ in, T* __restrict__ out, Geom g,
                                            int x0, int y0, int z0, int z1, uint32_t gate,
-                                           double inv9n)
+                                           double inv_div)
 {
     constexpr int H = 2 * R, LXE = TXW + 4 * R;
     if (pairs && x0 - H >= 0 && x0 - H + LXE <= g.nx)
-        mean9_tile_body<R, TY, T, GATE, TXW, true>(sm.p, in, out, g, x0, y0, z0, z1, gate, inv9n);
+        mean9_tile_body<R, TY, T, GATE, TXW, true, BOX>(sm.p, in, out, g, x0, y0, z0, z1, gate,
+                                                        inv_div);
     else
-        mean9_tile_body<R, TY, T, GATE, TXW, false>(sm.e, in, out, g, x0, y0, z0, z1, gate,
-                                                    inv9n);
+        mean9_tile_body<R, TY, T, GATE, TXW, false, BOX>(sm.e, in, out, g, x0, y0, z0, z1, gate,
+                                                         inv_div);
 }
 
 }  // namespace lnf

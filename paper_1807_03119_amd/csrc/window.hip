@@ -1,7 +1,7 @@
 // The paper's comparison filters (Section "Other Filters"), as second
 // workloads beside the nine-cluster filter:
-//   - mean (eq. 4): the separable cluster tile with a single centre cluster
-//     (cluster.hip, launch_box_mean);
+//   - mean (eq. 4): the box term of the MEAN9 streaming tile (mean9.hip,
+//     launch_box_mean);
 //   - sigma (eq. 5), Okada (eq. 6), entropy (eq. 7): data-dependent window
 //     filters, computed here by a direct window kernel.  A workgroup streams a
 //     32 x 8 output column down z with an LDS ring of the last 2r+1 raw planes
