@@ -101,7 +101,7 @@ template <int R, typename T, bool GATE>
 __global__ __launch_bounds__(256) void minvar9_multi(const BatchTable* __restrict__ tab, int cls,
                                                      uint32_t gate)
 {
-    __shared__ __align__(16) MV9Smem<R> sm;
+    __shared__ __align__(16) MV9Smem<R, T> sm;
     constexpr int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
     const BatchClass c = tab->c[cls];
     const int t = xcd_tile(blockIdx.x, c.total);
@@ -113,8 +113,9 @@ __global__ __launch_bounds__(256) void minvar9_multi(const BatchTable* __restric
     const int bz = rest / d.tiles_y;
     const Geom g{d.nx, d.ny, d.nz};
     const int z0 = bz * d.zs;
-    minvar9_tile<R, T, GATE>(sm, static_cast<const T*>(d.in), static_cast<T*>(d.out), g, bx * 32,
-                             by * 8, z0, min(z0 + d.zs, d.nz), gate, (double)n, 1.0 / n);
+    minvar9_tile<R, T, GATE>(sm, static_cast<const T*>(d.in), static_cast<T*>(d.out), g,
+                             bx * MV9Shape<R>::TX, by * MV9Shape<R>::TY, z0,
+                             min(z0 + d.zs, d.nz), gate, (double)n, 1.0 / n);
 }
 
 // A launchable class kernel: function, block size.

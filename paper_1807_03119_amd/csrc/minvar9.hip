@@ -13,22 +13,25 @@ __global__ __launch_bounds__(256) void minvar9_planes(const T* __restrict__ in, 
                                                       int total, uint32_t gate, double dn,
                                                       double invn)
 {
-    __shared__ __align__(16) MV9Smem<R> sm;
+    __shared__ __align__(16) MV9Smem<R, T> sm;
     const int tile = xcd_tile(blockIdx.x, total);
     const int bx = tile % tiles_x;
     const int rest = tile / tiles_x;
     const int by = rest % tiles_y;
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
-    minvar9_tile<R, T, GATE>(sm, in, out, g, bx * 32, by * 8, z0, min(z0 + zs, g.nz), gate, dn,
-                             invn);
+    minvar9_tile<R, T, GATE>(sm, in, out, g, bx * MV9Shape<R>::TX, by * MV9Shape<R>::TY, z0,
+                             min(z0 + zs, g.nz), gate, dn, invn);
 }
 
 template <int R, typename T>
 hipError_t launch_planes(const void* in, void* out, Geom g, uint32_t gate, int zs, hipStream_t s)
 {
-    const int tiles_x = (g.nx + 31) / 32, tiles_y = (g.ny + 7) / 8;
-    if (zs <= 0) zs = default_zs(tiles_x * tiles_y, g.nz, 2048);
+    using S = MV9Shape<R>;
+    const int tiles_x = (g.nx + S::TX - 1) / S::TX, tiles_y = (g.ny + S::TY - 1) / S::TY;
+    if (zs <= 0)
+        zs = default_zs(tiles_x * tiles_y, g.nz,
+                        resident_groups((const void*)minvar9_planes<R, T, false>, S::THREADS));
     const int nzs = (g.nz + zs - 1) / zs;
     const int total = tiles_x * tiles_y * nzs;
     const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
@@ -63,8 +66,8 @@ int minvar9_variants() { return 1; }
 void minvar9_tile_shape(int variant, int* tx, int* ty)
 {
     (void)variant;
-    *tx = 32;
-    *ty = 8;
+    *tx = MV9Shape<1>::TX;  // one tile shape for every radius
+    *ty = MV9Shape<1>::TY;
 }
 
 hipError_t launch_minvar9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
