@@ -18,13 +18,28 @@
 
 namespace lnf {
 
+// z-strip depth of a launch over tiles_xy tile columns.  The strip count
+// minimises (rounds of resident workgroups) x (slices per strip + the slices a
+// strip reads beyond its own), so the last round is not a thin tail; strips
+// are no shallower than 16 slices.
 int default_zs(int tiles_xy, int nz, int target_groups)
 {
     constexpr int kMinDepth = 16;  // shallower strips re-read too much z-halo
-    int nzs = (target_groups + tiles_xy - 1) / std::max(tiles_xy, 1);
+    constexpr int kHalo = 12;      // extra slices per strip (4r at r = 3)
+    tiles_xy = std::max(tiles_xy, 1);
+    target_groups = std::max(target_groups, 1);
     const int max_nzs = std::max(1, (nz + kMinDepth - 1) / kMinDepth);
-    nzs = std::min(std::max(nzs, 1), max_nzs);
-    return (nz + nzs - 1) / nzs;
+    int best = 1;
+    long long best_cost = -1;
+    for (int nzs = 1; nzs <= max_nzs; ++nzs) {
+        const long long rounds = ((long long)tiles_xy * nzs + target_groups - 1) / target_groups;
+        const long long cost = rounds * ((nz + nzs - 1) / nzs + kHalo);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = nzs;
+        }
+    }
+    return (nz + best - 1) / best;
 }
 
 int resident_groups(const void* kernel, int threads)

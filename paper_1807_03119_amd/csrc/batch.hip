@@ -98,7 +98,8 @@ __global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS)) void mean9_multi(
 }
 
 template <int R, typename T, bool GATE>
-__global__ __launch_bounds__(256) void minvar9_multi(const BatchTable* __restrict__ tab, int cls,
+__global__ __launch_bounds__(MV9Shape<R>::THREADS)
+__attribute__((amdgpu_waves_per_eu(MV9Shape<R>::WAVES))) void minvar9_multi(const BatchTable* __restrict__ tab, int cls,
                                                      uint32_t gate)
 {
     __shared__ __align__(16) MV9Smem<R, T> sm;
@@ -147,8 +148,8 @@ ClassKernel class_kernel_rt(int rule, bool gate, int variant)
 {
     if (rule == LNF_MEAN9)
         return gate ? mean9_kernel_v<R, T, true>(variant) : mean9_kernel_v<R, T, false>(variant);
-    if (gate) return {reinterpret_cast<const void*>(minvar9_multi<R, T, true>), 256};
-    return {reinterpret_cast<const void*>(minvar9_multi<R, T, false>), 256};
+    if (gate) return {reinterpret_cast<const void*>(minvar9_multi<R, T, true>), MV9Shape<R>::THREADS};
+    return {reinterpret_cast<const void*>(minvar9_multi<R, T, false>), MV9Shape<R>::THREADS};
 }
 
 template <typename T>

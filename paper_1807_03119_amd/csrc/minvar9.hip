@@ -8,7 +8,8 @@ namespace lnf {
 namespace {
 
 template <int R, typename T, bool GATE>
-__global__ __launch_bounds__(256) void minvar9_planes(const T* __restrict__ in, T* __restrict__ out,
+__global__ __launch_bounds__(MV9Shape<R>::THREADS)
+__attribute__((amdgpu_waves_per_eu(MV9Shape<R>::WAVES))) void minvar9_planes(const T* __restrict__ in, T* __restrict__ out,
                                                       Geom g, int zs, int tiles_x, int tiles_y,
                                                       int total, uint32_t gate, double dn,
                                                       double invn)
@@ -38,10 +39,10 @@ hipError_t launch_planes(const void* in, void* out, Geom g, uint32_t gate, int z
     const T* pin = static_cast<const T*>(in);
     T* pout = static_cast<T*>(out);
     if (gate)
-        hipLaunchKernelGGL((minvar9_planes<R, T, true>), dim3(total), dim3(256), 0, s,
+        hipLaunchKernelGGL((minvar9_planes<R, T, true>), dim3(total), dim3(S::THREADS), 0, s,
                            pin, pout, g, zs, tiles_x, tiles_y, total, gate, (double)n, 1.0 / n);
     else
-        hipLaunchKernelGGL((minvar9_planes<R, T, false>), dim3(total), dim3(256), 0, s,
+        hipLaunchKernelGGL((minvar9_planes<R, T, false>), dim3(total), dim3(S::THREADS), 0, s,
                            pin, pout, g, zs, tiles_x, tiles_y, total, gate, (double)n, 1.0 / n);
     return hipGetLastError();
 }

@@ -33,6 +33,7 @@
 // for uint8 data (Q <= 729 * 255^2 < 2^26).
 #pragma once
 
+#include <cstddef>
 #include <type_traits>
 
 #include "device_common.h"
@@ -40,15 +41,31 @@
 
 namespace lnf {
 
-// Row pitches: 32-bit arrays take 4 mod 8 words and 64-bit arrays 2 mod 4
-// elements, so eight consecutive rows start in eight different groups of four
-// LDS banks (16-byte reads of eight lanes per bank cycle are conflict free).
-constexpr int mv9_pitch32(int n) { return n + ((12 - n % 8) % 8); }
-constexpr int mv9_pitch64(int n) { return n + ((6 - n % 4) % 4); }
-template <typename Q>
-constexpr int mv9_pitch(int n)
+// LDS layout.  Bank conflicts come from lane groups that span two rows of an
+// array (the z-sum writes: 64 lanes over rows of TX+4r; the y-pass: lanes over
+// rows of TX+2r, one column segment after the other), and from 16-byte
+// accesses whose eight lanes per bank cycle fall in the same bank group.  The
+// pitches below make the rows such a group spans continue each other in bank
+// space, and give the eight rows of one 16-byte access distinct bank groups.
+//
+// Smallest pitch p >= lo with p = 2 mod 4 (when asked) and ys * p = g (mod m).
+constexpr int mv9_find_pitch(int ys, int g, int lo, int m, bool two_mod4)
 {
-    return sizeof(Q) == 4 ? mv9_pitch32(n) : mv9_pitch64(n);
+    for (int p = lo; p < lo + 64; ++p)
+        if ((!two_mod4 || p % 4 == 2) && (ys * p - g) % m == 0) return p;
+    return -1;
+}
+// The y-pass segment height: the smallest that fits the threads and admits
+// all three pitches; 0 if none does.
+constexpr int mv9_pick_ys(int gx, int gy, int xw, int threads)
+{
+    for (int ys = 1; ys <= gy; ++ys) {
+        if ((gy + ys - 1) / ys * gx > threads) continue;
+        if (mv9_find_pitch(ys, gx, xw, 32, true) > 0 && mv9_find_pitch(ys, gx, xw, 16, true) > 0 &&
+            mv9_find_pitch(ys, gx, gx, 32, false) > 0)
+            return ys;
+    }
+    return 0;
 }
 
 template <int R>
@@ -67,35 +84,49 @@ struct MV9Shape {
     static_assert(XR * NXS <= THREADS, "x-pass: one thread per row segment");
     static constexpr int XW = XS + 2 * R;           // raw values a segment reads
     static constexpr int XW4 = (XW + 3) / 4 * 4;    // ... rounded to 16-byte reads
-    static constexpr int XW2 = (XW + 1) / 2 * 2;    // ... of 64-bit values
+    // z-sum rows (32-bit words): the pitch is the row length when that is
+    // 4 mod 8 (rows continue each other, and eight rows of a 16-byte x-pass
+    // read start in distinct bank groups), else the next such length.  The
+    // x-pass reads XW4 words from each segment start, past the row end into
+    // the next row (those values only feed discarded centres).
+    static constexpr int ZP = LX + (12 - LX % 8) % 8;
+    static constexpr int ZN = ((LY - 1) * ZP + (NXS - 1) * XS + XW4 + 3) / 4 * 4;  // 16-byte multiple
     // y-pass: YS centre rows per column segment
-    static constexpr int NYS0 = THREADS / GX;
-    static constexpr int YS = (GY + NYS0 - 1) / NYS0;
+    static constexpr int YS = mv9_pick_ys(GX, GY, NXS * XS, THREADS);
+    static_assert(YS > 0, "no conflict-free y-pass layout");
     static constexpr int NYS = (GY + YS - 1) / YS;
     static constexpr int YW = YS + 2 * R;           // rows a segment reads
     static constexpr int XROWS = NYS * YS + 2 * R > LY ? NYS * YS + 2 * R : LY;
+    // x-pass output rows (written 8 bytes per lane by 16 consecutive rows)
+    // and centre planes: pitches whose rows YS apart continue each other
+    static constexpr int XPB = mv9_find_pitch(YS, GX, NXS * XS, 32, true);
+    static constexpr int XPD = mv9_find_pitch(YS, GX, NXS * XS, 16, true);  // 64-bit
+    static constexpr int VP = mv9_find_pitch(YS, GX, GX, 32, false);
     static constexpr int OPT = TX * TY / THREADS;   // outputs per thread
     static constexpr int OROWS = THREADS / TX;      // output rows per pass
     static constexpr int U = R + 1;                 // register ring period
+    // waves per SIMD the kernels are compiled for (r = 4 would spill at 3)
+    static constexpr int WAVES = R <= 3 ? 3 : 2;
     static_assert(THREADS % TX == 0 && OPT * OROWS == TY, "gather mapping");
 };
 
 template <int R, typename T>
 struct MV9Smem {
     using S = MV9Shape<R>;
+    // sums of squares: fp64 for uint16 data, staged in LDS as two 32-bit
+    // halves (so they share the 32-bit layout); uint32 for uint8 data
     using QT = std::conditional_t<sizeof(T) == 1, uint32_t, double>;
-    static constexpr int ZW = (S::NXS - 1) * S::XS + S::XW4;   // words a Zb row is read to
-    static constexpr int ZQW = (S::NXS - 1) * S::XS + (sizeof(QT) == 4 ? S::XW4 : S::XW2);
-    static constexpr int ZPB = mv9_pitch32(ZW > S::LX ? ZW : S::LX);
-    static constexpr int ZPQ = mv9_pitch<QT>(ZQW > S::LX ? ZQW : S::LX);
-    static constexpr int XPB = mv9_pitch32(S::NXS * S::XS);
-    static constexpr int XPQ = mv9_pitch<QT>(S::NXS * S::XS);
-    QT zq[S::LY * ZPQ];
-    QT xq[S::XROWS * XPQ];
-    double vv[S::GY * S::GX];
-    uint32_t zb[S::LY * ZPB];
-    uint32_t xb[S::XROWS * XPB];
-    uint32_t vo[S::GY * S::GX];
+    static constexpr bool WIDE = sizeof(QT) == 8;
+    static constexpr int XPQ = WIDE ? S::XPD : S::XPB;
+    // every array a multiple of 16 bytes, so each starts 16-byte aligned
+    static constexpr int a16(int n, int bytes) { return (n * bytes + 15) / 16 * 16 / bytes; }
+    QT xq[a16(S::XROWS * XPQ, sizeof(QT))];
+    double vv[a16(S::GY * S::VP, 8)];
+    uint32_t zb[S::ZN];
+    uint32_t zq0[S::ZN];               // uint8: Zq; uint16: low half of Zq
+    uint32_t zq1[WIDE ? S::ZN : 4];    // uint16: high half of Zq
+    uint32_t xb[a16(S::XROWS * S::XPB, 4)];
+    uint32_t vo[a16(S::GY * S::VP, 4)];
 };
 
 // dn = n, invn = 1/n.
@@ -107,6 +138,10 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R, T>& sm, const T* __restr
     using S = MV9Shape<R>;
     using SM = MV9Smem<R, T>;
     using QT = typename SM::QT;
+    static_assert(offsetof(SM, vv) % 16 == 0 && offsetof(SM, zb) % 16 == 0 &&
+                      offsetof(SM, zq0) % 16 == 0 && offsetof(SM, zq1) % 16 == 0 &&
+                      offsetof(SM, xb) % 16 == 0 && offsetof(SM, vo) % 16 == 0,
+                  "16-byte LDS accesses need 16-byte aligned arrays");
     constexpr int kT = S::THREADS, LX = S::LX, GX = S::GX, XS = S::XS, YS = S::YS;
     constexpr int U = S::U, OPT = S::OPT;
     const int tid = threadIdx.x;
@@ -115,15 +150,14 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R, T>& sm, const T* __restr
 
     // ---- raw columns owned for the z-sums
     uint32_t off[S::NZ];
-    int zbi[S::NZ], zqi[S::NZ];  // LDS indexes of each owned column
+    int zi[S::NZ];  // LDS index of each owned column
 #pragma unroll
     for (int i = 0; i < S::NZ; ++i) {
         const int e = min(tid + i * kT, S::NRAW - 1);
         const int row = e / LX, col = e - row * LX;
         off[i] = (uint32_t)(clampi(y0 - S::H + row, 0, g.ny - 1) * g.nx +
                             clampi(x0 - S::H + col, 0, g.nx - 1)) * (uint32_t)sizeof(T);
-        zbi[i] = row * SM::ZPB + col;
-        zqi[i] = row * SM::ZPQ + col;
+        zi[i] = row * S::ZP + col;
     }
     // lanes past the tile in the last round own no column
     const bool zlast = tid + (S::NZ - 1) * kT < S::NRAW;
@@ -209,8 +243,14 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R, T>& sm, const T* __restr
 #pragma unroll
             for (int i = 0; i < S::NZ; ++i) {
                 if (i < S::NZ - 1 || zlast) {
-                    sm.zb[zbi[i]] = zb[i];
-                    sm.zq[zqi[i]] = zq[i];
+                    sm.zb[zi[i]] = zb[i];
+                    if constexpr (SM::WIDE) {
+                        const uint64_t w = __builtin_bit_cast(uint64_t, zq[i]);
+                        sm.zq0[zi[i]] = (uint32_t)w;
+                        sm.zq1[zi[i]] = (uint32_t)(w >> 32);
+                    } else {
+                        sm.zq0[zi[i]] = zq[i];
+                    }
                 }
             }
             barrier_lds();
@@ -218,43 +258,35 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R, T>& sm, const T* __restr
             // 2. x-pass: centre column c of the region covers raw columns c .. c+2r
             if (xact) {
                 const int cbase = xseg * XS;
-                uint32_t wb[S::XW4];
-                QT wq[S::XW4];
-                const uint32_t* rb = sm.zb + xrow * SM::ZPB + cbase;
-                const QT* rq = sm.zq + xrow * SM::ZPQ + cbase;
-#pragma unroll
-                for (int i = 0; i < S::XW4; i += 4) {
-                    const uint4 t = *reinterpret_cast<const uint4*>(rb + i);
-                    wb[i] = t.x;
-                    wb[i + 1] = t.y;
-                    wb[i + 2] = t.z;
-                    wb[i + 3] = t.w;
-                }
-                if constexpr (sizeof(QT) == 4) {
+                const int zr = xrow * S::ZP + cbase;
+                uint32_t wb[S::XW4], w0[S::XW4], w1[S::XW4];
+                auto read_row = [&](const uint32_t* src, uint32_t(&w)[S::XW4]) {
 #pragma unroll
                     for (int i = 0; i < S::XW4; i += 4) {
-                        const uint4 t = *reinterpret_cast<const uint4*>(rq + i);
-                        wq[i] = t.x;
-                        wq[i + 1] = t.y;
-                        wq[i + 2] = t.z;
-                        wq[i + 3] = t.w;
+                        const uint4 t = *reinterpret_cast<const uint4*>(src + zr + i);
+                        w[i] = t.x;
+                        w[i + 1] = t.y;
+                        w[i + 2] = t.z;
+                        w[i + 3] = t.w;
                     }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < S::XW2; i += 2) {
-                        const double2 t = *reinterpret_cast<const double2*>(rq + i);
-                        wq[i] = t.x;
-                        wq[i + 1] = t.y;
-                    }
-                }
+                };
+                read_row(sm.zb, wb);
+                read_row(sm.zq0, w0);
+                if constexpr (SM::WIDE) read_row(sm.zq1, w1);
+                auto wq = [&](int i) -> QT {
+                    if constexpr (SM::WIDE)
+                        return __builtin_bit_cast(double, ((uint64_t)w1[i] << 32) | w0[i]);
+                    else
+                        return w0[i];
+                };
                 uint32_t cb[S::XW];
                 QT cq[S::XW];
                 cb[0] = wb[0];
-                cq[0] = wq[0];
+                cq[0] = wq(0);
 #pragma unroll
                 for (int i = 1; i < S::XW; ++i) {
                     cb[i] = cb[i - 1] + wb[i];
-                    cq[i] = cq[i - 1] + wq[i];
+                    cq[i] = cq[i - 1] + wq(i);
                 }
                 uint32_t ob[XS];
                 QT oq[XS];
@@ -263,20 +295,15 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R, T>& sm, const T* __restr
                     ob[m] = cb[m + 2 * R] - (m ? cb[m - 1] : 0u);
                     oq[m] = cq[m + 2 * R] - (m ? cq[m - 1] : (QT)0);
                 }
-                uint32_t* db = sm.xb + xrow * SM::XPB + cbase;
+                uint32_t* db = sm.xb + xrow * S::XPB + cbase;
                 QT* dq = sm.xq + xrow * SM::XPQ + cbase;
 #pragma unroll
-                for (int m = 0; m < XS; m += 4)
-                    *reinterpret_cast<uint4*>(db + m) = make_uint4(ob[m], ob[m + 1], ob[m + 2], ob[m + 3]);
-                if constexpr (sizeof(QT) == 4) {
-#pragma unroll
-                    for (int m = 0; m < XS; m += 4)
-                        *reinterpret_cast<uint4*>(dq + m) =
-                            make_uint4(oq[m], oq[m + 1], oq[m + 2], oq[m + 3]);
-                } else {
-#pragma unroll
-                    for (int m = 0; m < XS; m += 2)
+                for (int m = 0; m < XS; m += 2) {
+                    *reinterpret_cast<uint2*>(db + m) = make_uint2(ob[m], ob[m + 1]);
+                    if constexpr (SM::WIDE)
                         *reinterpret_cast<double2*>(dq + m) = make_double2(oq[m], oq[m + 1]);
+                    else
+                        *reinterpret_cast<uint2*>(dq + m) = make_uint2(oq[m], oq[m + 1]);
                 }
             }
             barrier_lds();
@@ -288,7 +315,7 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R, T>& sm, const T* __restr
                 QT cq[S::YW];
 #pragma unroll
                 for (int t = 0; t < S::YW; ++t) {
-                    const uint32_t b = sm.xb[(rbase + t) * SM::XPB + ycol];
+                    const uint32_t b = sm.xb[(rbase + t) * S::XPB + ycol];
                     const QT qv = sm.xq[(rbase + t) * SM::XPQ + ycol];
                     cb[t] = t ? cb[t - 1] + b : b;
                     cq[t] = t ? cq[t - 1] + qv : qv;
@@ -300,8 +327,8 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R, T>& sm, const T* __restr
                         const uint32_t b = cb[m + 2 * R] - (m ? cb[m - 1] : 0u);
                         const QT qv = cq[m + 2 * R] - (m ? cq[m - 1] : (QT)0);
                         const double db = (double)b;
-                        sm.vv[gy * GX + ycol] = __builtin_fma(dn, (double)qv, -db * db);
-                        sm.vo[gy * GX + ycol] = round_div_odd(b, invn);
+                        sm.vv[gy * S::VP + ycol] = __builtin_fma(dn, (double)qv, -db * db);
+                        sm.vo[gy * S::VP + ycol] = round_div_odd(b, invn);
                     }
                 }
             }
@@ -314,14 +341,14 @@ __device__ __forceinline__ void minvar9_tile(MV9Smem<R, T>& sm, const T* __restr
 #pragma unroll
             for (int j = 0; j < OPT; ++j) {
                 const int oy = oyb + j * S::OROWS;
-                const int ic = (oy + R) * GX + ox + R;
+                const int ic = (oy + R) * S::VP + ox + R;
                 const double cv = sm.vv[ic];
                 const uint32_t co = sm.vo[ic];
-                double gv = sm.vv[oy * GX + ox];
-                uint32_t go = sm.vo[oy * GX + ox];
+                double gv = sm.vv[oy * S::VP + ox];
+                uint32_t go = sm.vo[oy * S::VP + ox];
 #pragma unroll
                 for (int k = 1; k < 4; ++k) {
-                    const int ik = (oy + ((k & 2) ? 2 * R : 0)) * GX + ox + ((k & 1) ? 2 * R : 0);
+                    const int ik = (oy + ((k & 2) ? 2 * R : 0)) * S::VP + ox + ((k & 1) ? 2 * R : 0);
                     const double v = sm.vv[ik];
                     if (v < gv) {
                         gv = v;
