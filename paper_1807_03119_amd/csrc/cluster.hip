@@ -1,46 +1,49 @@
 // Geometry variants of the nine-cluster filter (cross clusters of eq. 2, and
-// diagonal offsets 1 or 2r+1): single-volume kernels around the cluster-gather
-// tile of cluster_tile.h.  The default geometry (cubes at offset r) runs on
-// the MEAN9 / MINVAR9 kernels instead.
-#include "cluster_tile.h"
+// diagonal offsets 1 or 2r+1), both rules: single-volume kernels around the
+// per-plane cluster tile of plane_tile.h.  The default geometry (cubes at
+// offset r) runs on the MEAN9 streaming kernel and the MINVAR9 kernel instead.
 #include "device_common.h"
 #include "lnf.h"
 #include "lnf_internal.h"
+#include "plane_tile.h"
 
 namespace lnf {
 namespace {
 
+// The gate is a runtime value here (0 = off): one instantiation per geometry.
 template <int R, int D, int SHAPE, int RULE, typename T>
-__global__ __launch_bounds__(256) void cluster_planes(const T* __restrict__ in,
-                                                      T* __restrict__ out, Geom g, int zs,
-                                                      int tiles_x, int tiles_y, int total,
-                                                      uint32_t gate)
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(PTShape<R, D, SHAPE, RULE>::WAVES))) void cluster_planes(
+    const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
+    int total, uint32_t gate, double dn, double inv)
 {
-    constexpr bool VAR = RULE == kRuleMinVar9;
-    using S = CTShape<R, D, SHAPE, VAR>;
-    __shared__ __align__(16) CTSmem<R, D, SHAPE, VAR> sm;
+    using S = PTShape<R, D, SHAPE, RULE>;
+    __shared__ __align__(16) PTSmem<R, D, SHAPE, RULE, T> sm;
     const int tile = xcd_tile(blockIdx.x, total);
     const int bx = tile % tiles_x;
     const int rest = tile / tiles_x;
     const int by = rest % tiles_y;
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
-    cluster_tile<R, D, SHAPE, RULE, T>(sm, in, out, g, bx * S::TX, by * S::TY, z0,
-                                       min(z0 + zs, g.nz), gate);
+    plane_tile<R, D, SHAPE, RULE, T, true>(sm, in, out, g, bx * S::TX, by * S::TY, z0,
+                                           min(z0 + zs, g.nz), gate, dn, inv);
 }
 
 template <int R, int D, int SHAPE, int RULE, typename T>
 hipError_t launch_geom(const void* in, void* out, Geom g, uint32_t gate, int zs, hipStream_t s)
 {
-    using S = CTShape<R, D, SHAPE, RULE == kRuleMinVar9>;
+    using S = PTShape<R, D, SHAPE, RULE>;
+    static_assert(S::THREADS == 256, "launch shape");
     const auto kern = cluster_planes<R, D, SHAPE, RULE, T>;
     const int tiles_x = (g.nx + S::TX - 1) / S::TX, tiles_y = (g.ny + S::TY - 1) / S::TY;
     if (zs <= 0)
-        zs = default_zs(tiles_x * tiles_y, g.nz, resident_groups((const void*)kern, 256));
+        zs = default_zs(tiles_x * tiles_y, g.nz, resident_groups((const void*)kern, S::THREADS));
     const int nzs = (g.nz + zs - 1) / zs;
     const int total = tiles_x * tiles_y * nzs;
-    hipLaunchKernelGGL(kern, dim3(total), dim3(256), 0, s, static_cast<const T*>(in),
-                       static_cast<T*>(out), g, zs, tiles_x, tiles_y, total, gate);
+    const double dn = (double)S::N;
+    const double inv = S::VAR ? 1.0 / S::N : 1.0 / (9.0 * S::N);
+    hipLaunchKernelGGL(kern, dim3(total), dim3(S::THREADS), 0, s, static_cast<const T*>(in),
+                       static_cast<T*>(out), g, zs, tiles_x, tiles_y, total, gate, dn, inv);
     return hipGetLastError();
 }
 

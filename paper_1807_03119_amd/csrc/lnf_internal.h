@@ -37,7 +37,7 @@ inline bool mean9_pairs_ok(const void* base, int nx, size_t elem)
     return nx % 2 == 0 && reinterpret_cast<uintptr_t>(base) % (2 * elem) == 0;
 }
 
-// ---- geometry variants (cluster_tile.h): LNF_GEOM_* bits, both rules -------
+// ---- geometry variants (plane_tile.h): LNF_GEOM_* bits, both rules ---------
 hipError_t launch_geometry(int rule, uint32_t geom, const void* in, void* out, int dtype, int r,
                            Geom g, uint32_t gate, int zs, hipStream_t s);
 // The paper's mean filter (eq. 4): rounded mean of the (2r+1)^3 cube, gated.
