@@ -326,6 +326,27 @@ def main():
             extras[f"compare_r1_{name}_ms"] = ms2
         extras["compare_r1_sigma_half_width"] = hw
         g.close()
+        log("timing the Otsu pipeline and the surface-point mode")
+        g = Filter(_lib.LNF_MEAN9, 0)
+        ms2, _ = time_launches(lambda: g.histogram(vol), 10, 2, stream)
+        extras["otsu"] = {"histogram_ms": ms2, "histogram_GBps": nvox * 2 / (ms2 * 1e-3) / 1e9}
+        _, t_otsu = g.filter_otsu(vol, args.radius, out=out)
+        ms2, _ = time_launches(lambda: g.filter_otsu(vol, args.radius, out=out), 5, 1, stream)
+        extras["otsu"].update({"threshold": int(t_otsu), "pipeline_ms": ms2,
+                               "pipeline_Gvox_s": nvox / (ms2 * 1e-3) / 1e9,
+                               "pipeline": "histogram, exact Otsu on the host, gated MEAN9 "
+                                           f"r={args.radius}"})
+        g.close()
+        gen = torch.Generator(device="cuda").manual_seed(SEED + 1)
+        npts = 1 << 20  # one value per pixel of a 1024 x 1024 view
+        xyz = torch.randint(0, DIMS[0], (npts, 3), generator=gen, device="cuda", dtype=torch.int32)
+        extras["points"] = {"points": npts, "sample": "uniform random voxels of the volume"}
+        for rule_name, rc in (("mean9", _lib.LNF_MEAN9), ("minvar9", _lib.LNF_MINVAR9)):
+            g = Filter(rc, 0)
+            ms2, _ = time_launches(lambda: g.points(vol, args.radius, xyz), 5, 1, stream)
+            extras["points"][f"{rule_name}_r{args.radius}_ms"] = ms2
+            extras["points"][f"{rule_name}_r{args.radius}_Mpoints_s"] = npts / (ms2 * 1e-3) / 1e6
+            g.close()
         log("timing the 64-volume mixed batch")
         extras["batch64"] = batch_benchmark(rule_code, stream)
         res["extras"] = extras

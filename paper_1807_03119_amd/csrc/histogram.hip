@@ -6,8 +6,9 @@
 // atomics once per workgroup:
 //   - uint8: 256 uint32 counters per workgroup;
 //   - uint16: 65536 bins as two 16-bit counters per LDS word (128 KiB of the
-//     160 KiB LDS); a workgroup takes at most 65535 voxels, so neither half of
-//     a word can carry into the other.
+//     160 KiB LDS, one 1024-thread workgroup per CU); a workgroup takes at
+//     most 65528 voxels (eight per 16-byte load), so neither half of a word
+//     can carry into the other.
 // The output histogram is cleared by a fill kernel (no memset node), so the
 // sequence can be captured in a graph.
 #include <hip/hip_runtime.h>
@@ -26,7 +27,8 @@ namespace lnf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kChunk16 = 65535;  // voxels per workgroup for the uint16 histogram
+constexpr int kThreads16 = 1024;  // uint16: one 128 KiB workgroup per CU, 16 waves
+constexpr int kChunk16 = 65528;   // voxels per uint16 workgroup: below 65536, a multiple of 8
 
 __global__ __launch_bounds__(kThreads) void fill_u64(unsigned long long* p, int n)
 {
@@ -47,20 +49,37 @@ __global__ __launch_bounds__(kThreads) void hist_u8(const uint8_t* __restrict__ 
     if (c) atomicAdd(&hist[threadIdx.x], (unsigned long long)c);
 }
 
-__global__ __launch_bounds__(kThreads) void hist_u16(const uint16_t* __restrict__ in, size_t n,
-                                                      unsigned long long* hist)
+__global__ __launch_bounds__(kThreads16) void hist_u16(const uint16_t* __restrict__ in, size_t n,
+                                                        unsigned long long* hist, int vec)
 {
     __shared__ uint32_t pairs[32768];  // bin 2i in the low half, bin 2i+1 in the high half
-    for (int i = threadIdx.x; i < 32768; i += kThreads) pairs[i] = 0;
+    for (int i = threadIdx.x; i < 32768; i += kThreads16) pairs[i] = 0;
     __syncthreads();
     const size_t begin = (size_t)blockIdx.x * kChunk16;
     const size_t end = begin + kChunk16 < n ? begin + kChunk16 : n;
-    for (size_t i = begin + threadIdx.x; i < end; i += kThreads) {
-        const uint32_t v = in[i];
-        atomicAdd(&pairs[v >> 1], (v & 1) ? 65536u : 1u);
+    auto add = [&](uint32_t v) { atomicAdd(&pairs[v >> 1], (v & 1) ? 65536u : 1u); };
+    size_t tail = begin;
+    if (vec) {
+        // 16-byte aligned volume: eight voxels per load (begin is a multiple
+        // of 8 voxels, so every workgroup's range starts aligned)
+        const size_t nv = (end - begin) / 8;
+        const uint4* p = reinterpret_cast<const uint4*>(in + begin);
+        for (size_t i = threadIdx.x; i < nv; i += kThreads16) {
+            const uint4 w = p[i];
+            add(w.x & 0xffffu);
+            add(w.x >> 16);
+            add(w.y & 0xffffu);
+            add(w.y >> 16);
+            add(w.z & 0xffffu);
+            add(w.z >> 16);
+            add(w.w & 0xffffu);
+            add(w.w >> 16);
+        }
+        tail = begin + nv * 8;
     }
+    for (size_t i = tail + threadIdx.x; i < end; i += kThreads16) add(in[i]);
     __syncthreads();
-    for (int i = threadIdx.x; i < 32768; i += kThreads) {
+    for (int i = threadIdx.x; i < 32768; i += kThreads16) {
         const uint32_t w = pairs[i];
         if (w & 0xffffu) atomicAdd(&hist[2 * i], (unsigned long long)(w & 0xffffu));
         if (w >> 16) atomicAdd(&hist[2 * i + 1], (unsigned long long)(w >> 16));
@@ -136,6 +155,9 @@ uint32_t otsu_from_hist(const uint64_t* hist, int levels)
     int best_t = -1;
     Big best_num, best_den;
     for (int t = 1; t < levels; ++t) {
+        // an empty level t-1 leaves both classes, so the criterion, as they
+        // were at t-1: a tie, which the lower threshold keeps
+        if (!hist[t - 1]) continue;
         n0 += hist[t - 1];
         s0 += (unsigned __int128)hist[t - 1] * (unsigned)(t - 1);
         const unsigned __int128 n1 = N - n0;
@@ -170,8 +192,9 @@ hipError_t launch_histogram(const void* vol, size_t n, int dtype, uint64_t* hist
                            static_cast<const uint8_t*>(vol), n, chunk, h);
     } else {
         const size_t groups = (n + kChunk16 - 1) / kChunk16;
-        hipLaunchKernelGGL(hist_u16, dim3((unsigned)groups), dim3(kThreads), 0, s,
-                           static_cast<const uint16_t*>(vol), n, h);
+        const int vec = (reinterpret_cast<uintptr_t>(vol) % 16) == 0;
+        hipLaunchKernelGGL(hist_u16, dim3((unsigned)groups), dim3(kThreads16), 0, s,
+                           static_cast<const uint16_t*>(vol), n, h, vec);
     }
     return hipGetLastError();
 }
