@@ -37,6 +37,10 @@ __global__ __launch_bounds__(kWThreads) void window_planes(const T* __restrict__
     constexpr int LX = kWX + 2 * R, LY = kWY + 2 * R, NPL = 2 * R + 1;
     constexpr int NRAW = LX * LY, NLOAD = (NRAW + kWThreads - 1) / kWThreads;
     constexpr bool ENT = KIND == kWinEntropy;
+    // planes of the window loop unrolled only at r = 1: a fully unrolled
+    // (2r+1)^3 window hoists all its LDS reads (266 VGPRs at r = 3)
+    constexpr int UZ = R <= 1 ? NPL : 1;
+    constexpr int UY = R <= 2 ? NPL : 1;  // entropy rows (64-bit weights) likewise beyond r = 2
     __shared__ uint32_t raw[NPL][NRAW];
     __shared__ int64_t wts[ENT ? NPL : 1][ENT ? NRAW : 1];
 
@@ -102,7 +106,13 @@ __global__ __launch_bounds__(kWThreads) void window_planes(const T* __restrict__
                 }
                 o = cnt ? (uint32_t)((double)(2 * sum + cnt) / (double)(2 * cnt)) : 0u;
             } else if constexpr (KIND == kWinSigma) {
+                // |w - p0| <= param  <=>  lo <= w <= hi, tested as one unsigned
+                // compare (w - lo) <= hi - lo (values and bounds below 2^32)
+                const uint64_t hi64 = (uint64_t)p0 + (uint64_t)param;
+                const uint32_t lo = (int64_t)p0 > param ? (uint32_t)((int64_t)p0 - param) : 0u;
+                const uint32_t span = (uint32_t)(hi64 < 0xffffffffull ? hi64 : 0xffffffffull) - lo;
                 uint32_t sum = 0, cnt = 0;
+#pragma unroll UZ
                 for (int dz = 0; dz < NPL; ++dz) {
                     const uint32_t* pl = raw[(k - 2 * R + dz) % NPL];
 #pragma unroll
@@ -110,11 +120,9 @@ __global__ __launch_bounds__(kWThreads) void window_planes(const T* __restrict__
 #pragma unroll
                         for (int dx = 0; dx <= 2 * R; ++dx) {
                             const uint32_t w = pl[(oy + dy) * LX + ox + dx];
-                            const uint32_t d = w > p0 ? w - p0 : p0 - w;
-                            if ((int64_t)d <= param) {
-                                sum += w;
-                                cnt += 1;
-                            }
+                            const bool in = w - lo <= span;
+                            sum += in ? w : 0u;
+                            cnt += in ? 1u : 0u;
                         }
                 }
                 // (2 sum + cnt) / (2 cnt) < 2^27 / 2: its fp64 quotient never
@@ -122,9 +130,10 @@ __global__ __launch_bounds__(kWThreads) void window_planes(const T* __restrict__
                 o = (uint32_t)((double)(2 * sum + cnt) / (double)(2 * cnt));
             } else {
                 int64_t h = 0;
+#pragma unroll UZ
                 for (int dz = 0; dz < NPL; ++dz) {
                     const int64_t* pl = wts[(k - 2 * R + dz) % NPL];
-#pragma unroll
+#pragma unroll UY
                     for (int dy = 0; dy <= 2 * R; ++dy)
 #pragma unroll
                         for (int dx = 0; dx <= 2 * R; ++dx) h += pl[(oy + dy) * LX + ox + dx];
