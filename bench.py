@@ -326,6 +326,20 @@ def main():
             extras[f"compare_r1_{name}_ms"] = ms2
         extras["compare_r1_sigma_half_width"] = hw
         g.close()
+        log("timing the at-scale volume 1024 x 1024 x 1536 (r=3, both rules)")
+        big_dims = (1024, 1024, 1536)
+        big = phantom.ct_u12(big_dims, seed=3000, device="cuda")
+        big_out = torch.empty_like(big)
+        extras["scale_1024x1024x1536"] = {}
+        for rule_name, rc in (("mean9", _lib.LNF_MEAN9), ("minvar9", _lib.LNF_MINVAR9)):
+            g = Filter(rc, 0)
+            ms2, _ = time_launches(lambda: g(big, 3, out=big_out), 5, 1, stream)
+            gv = big.numel() / (ms2 * 1e-3) / 1e9
+            extras["scale_1024x1024x1536"][rule_name] = {
+                "ms": ms2, "Gvox_s": gv, "hbm_frac": gv * 4 / HBM_PEAK_GBS}
+            g.close()
+        del big, big_out
+        torch.cuda.empty_cache()
         log("timing the Otsu pipeline and the surface-point mode")
         g = Filter(_lib.LNF_MEAN9, 0)
         ms2, _ = time_launches(lambda: g.histogram(vol), 10, 2, stream)

@@ -182,7 +182,24 @@ def test_full_512cube_u12_sampled(filters, r, rule):
 
 
 def test_full_1024x1024x1536_u12_sampled(filters):
-    _full_size(filters, (1024, 1024, 1536), 3, "mean9", seed=3000, m=8000)
+    """The at-scale volume (3 GiB), both rules, r=3; outputs sampled on the device."""
+    dims = (1024, 1024, 1536)
+    vol_dev = ph.ct_u12(dims, seed=3000, device="cuda")
+    vol = vol_dev.cpu().numpy()
+    pts = _sample_points(dims, 8000, 3003)
+    idx = torch.from_numpy(pts.astype(np.int64)).cuda()
+    for rule in ("mean9", "minvar9"):
+        out = filters(rule)(vol_dev, 3)
+        # torch has no uint16 gather on the device: gather the same bits as int16
+        g = out.view(torch.int16)[idx[:, 2], idx[:, 1], idx[:, 0]].cpu().numpy()
+        g = g.view(np.uint16).astype(np.uint32)
+        del out
+        want = oracle.filter_points(vol, 3, pts, RULES[rule][1])
+        if not np.array_equal(g, want):
+            i = int(np.nonzero(g != want)[0][0])
+            raise AssertionError(f"{dims} r=3 {rule}: {int((g != want).sum())} of {len(pts)} "
+                                 f"samples differ; first at {pts[i].tolist()}: gpu {g[i]} "
+                                 f"oracle {want[i]}")
 
 
 def test_largest_plane_u8(filters):
