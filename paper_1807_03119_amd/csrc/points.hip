@@ -3,11 +3,15 @@
 // inside the renderer (Section "Our Method"; Results, Performance), so the
 // work is a sparse gather rather than a dense stencil.
 //
-// One 64-lane wavefront per point: the lanes split the (2r+1)^3 samples of each
-// of the nine clusters (coordinates clamped into the volume), keep per-cluster
-// partial sums (and sums of squares for MINVAR9) in registers, and combine them
-// with butterfly wavefront reductions (cross-lane shuffles).  Lane 0 applies
-// the rule, rounding and gate.
+// One 64-lane wavefront per point.  The nine clusters cover the (4r+1)^3 block
+// around the point (coordinates clamped into the volume); the lanes split its
+// (4r+1)^2 x-rows.  Each row is read once and summed over three x-ranges: left
+// [-2r, 0], right [0, 2r] and centre [-r, r].  A row at (dy, dz) then belongs to
+// the corner clusters whose y- and z-ranges hold it (left or right part by the
+// cluster's x side) and, when |dy|, |dz| <= r, to the centre cluster.  Per-lane
+// cluster sums (and sums of squares for MINVAR9) are combined with butterfly
+// wavefront reductions (cross-lane shuffles); MEAN9 needs only their total.
+// Lane 0 applies the rule, rounding and gate.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -39,45 +43,74 @@ __global__ __launch_bounds__(64 * kWaves) void filter_points_kernel(const T* __r
                                                                      uint32_t* out)
 {
     constexpr int M = 2 * R + 1, NB = M * M * M;
+    constexpr int W = 4 * R + 1, NROW = W * W;  // side and x-rows of the nine clusters' block
+    constexpr bool VAR = RULE == LNF_MINVAR9;
     const int lane = threadIdx.x & 63;
     const int64_t p = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (p >= n) return;  // whole wavefront exits together
-    const int px = xyz[3 * p], py = xyz[3 * p + 1], pz = xyz[3 * p + 2];
+    // the point is the same for the whole wavefront: keep it scalar
+    const int px = __builtin_amdgcn_readfirstlane(xyz[3 * p]);
+    const int py = __builtin_amdgcn_readfirstlane(xyz[3 * p + 1]);
+    const int pz = __builtin_amdgcn_readfirstlane(xyz[3 * p + 2]);
     if (px < 0 || py < 0 || pz < 0 || px >= g.nx || py >= g.ny || pz >= g.nz) {
         if (lane == 0) out[p] = 0xffffffffu;  // point outside the volume
         return;
     }
     const size_t nx = g.nx, plane = (size_t)g.nx * g.ny;
+    int xs[W];  // clamped x of the row's samples (the same for every row)
+#pragma unroll
+    for (int i = 0; i < W; ++i) xs[i] = clampi(px - 2 * R + i, 0, g.nx - 1);
     uint32_t s[9];
     double q[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const int j = k - 1;
-        const int dx = k == 0 ? 0 : ((j & 1) ? R : -R);
-        const int dy = k == 0 ? 0 : ((j & 2) ? R : -R);
-        const int dz = k == 0 ? 0 : ((j & 4) ? R : -R);
-        uint32_t acc = 0;
-        double acq = 0.0;
-        for (int e = lane; e < NB; e += 64) {
-            const int ax = e % M - R, ay = (e / M) % M - R, az = e / (M * M) - R;
-            const int x = clampi(px + dx + ax, 0, g.nx - 1);
-            const int y = clampi(py + dy + ay, 0, g.ny - 1);
-            const int z = clampi(pz + dz + az, 0, g.nz - 1);
-            const uint32_t v = in[(size_t)z * plane + (size_t)y * nx + x];
-            acc += v;
-            if (RULE == LNF_MINVAR9) acq = __builtin_fma((double)v, (double)v, acq);
-        }
-        s[k] = wave_sum_u32(acc);
-        if (RULE == LNF_MINVAR9) q[k] = wave_sum_f64(acq);
+        s[k] = 0;
+        q[k] = 0.0;
     }
-    if (lane != 0) return;
+    for (int row = lane; row < NROW; row += 64) {
+        const int dy = row % W - 2 * R, dz = row / W - 2 * R;
+        const int y = clampi(py + dy, 0, g.ny - 1), z = clampi(pz + dz, 0, g.nz - 1);
+        const T* rp = in + (size_t)z * plane + (size_t)y * nx;
+        uint32_t v[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) v[i] = rp[xs[i]];
+        uint32_t left = 0, right = 0, centre = 0;
+        double ql = 0.0, qr = 0.0, qc = 0.0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            if (i <= 2 * R) left += v[i];
+            if (i >= 2 * R) right += v[i];
+            if (i >= R && i <= 3 * R) centre += v[i];
+            if constexpr (VAR) {
+                const double vv = (double)v[i] * (double)v[i];  // exact below 2^32
+                if (i <= 2 * R) ql += vv;
+                if (i >= 2 * R) qr += vv;
+                if (i >= R && i <= 3 * R) qc += vv;
+            }
+        }
+        const bool inc = dy >= -R && dy <= R && dz >= -R && dz <= R;
+        s[0] += inc ? centre : 0u;
+        if constexpr (VAR) q[0] += inc ? qc : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {  // cluster j + 1: x, y, z side by bits 0, 1, 2
+            const bool in_yz = ((j & 2) ? dy >= 0 : dy <= 0) && ((j & 4) ? dz >= 0 : dz <= 0);
+            s[j + 1] += in_yz ? ((j & 1) ? right : left) : 0u;
+            if constexpr (VAR) q[j + 1] += in_yz ? ((j & 1) ? qr : ql) : 0.0;
+        }
+    }
     uint32_t o;
-    if (RULE == LNF_MEAN9) {
+    if constexpr (!VAR) {
         uint32_t total = 0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) total += s[k];
+        total = wave_sum_u32(total);
         o = round_div_odd(total, 1.0 / (9.0 * NB));
     } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            s[k] = wave_sum_u32(s[k]);
+            q[k] = wave_sum_f64(q[k]);
+        }
         uint32_t best_s = s[0];
         double best_v = __builtin_fma((double)NB, q[0], -(double)s[0] * (double)s[0]);
 #pragma unroll
@@ -90,6 +123,7 @@ __global__ __launch_bounds__(64 * kWaves) void filter_points_kernel(const T* __r
         }
         o = round_div_odd(best_s, 1.0 / NB);
     }
+    if (lane != 0) return;
     if (o < gate) o = 0;
     out[p] = o;
 }

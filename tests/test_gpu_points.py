@@ -40,3 +40,25 @@ def test_points_u8_and_outside_points():
     want = oracle.filter_points(vol, 2, pts[:2].astype(np.int64))
     np.testing.assert_array_equal(got[:2], want)
     assert np.all(got[2:] == 0xFFFFFFFF)
+
+
+@pytest.mark.parametrize("rule,orule", [(_lib.LNF_MEAN9, oracle.MEAN9),
+                                        (_lib.LNF_MINVAR9, oracle.MINVAR9)])
+def test_points_extremes_and_tiny_volumes(rule, orule):
+    """Full-range values (sum and variance limits) and volumes smaller than a
+    cluster, where every sample is clamped; every voxel of each volume."""
+    from paper_1807_03119_amd.api import Filter
+    vols = [ph.random_volume((19, 13, 11), np.uint16, seed=91, kind="extreme"),
+            ph.random_volume((1, 1, 1), np.uint16, seed=92, kind="uniform"),
+            ph.random_volume((2, 1, 3), np.uint8, seed=93, kind="uniform"),
+            ph.random_volume((5, 7, 2), np.uint8, seed=94, kind="extreme")]
+    with Filter(rule, 0) as f:
+        for vol in vols:
+            nz, ny, nx = vol.shape
+            zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+            pts = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], 1).astype(np.int32)
+            dev = torch.from_numpy(vol).cuda()
+            for r in (1, 2, 3, 4):
+                got = f.points(dev, r, torch.from_numpy(pts)).cpu().numpy().astype(np.uint32)
+                want = oracle.filter_points(vol, r, pts.astype(np.int64), orule)
+                np.testing.assert_array_equal(got, want, err_msg=f"{vol.shape} r={r}")
