@@ -151,11 +151,129 @@ __global__ __launch_bounds__(kWThreads) void window_planes(const T* __restrict__
     }
 }
 
+// Entropy (eq. 7) as a box sum: the window's sum of per-voxel weights
+// -p log2 p is the (2r+1)^3 box sum of the weight volume, computed separably.
+// Each thread keeps, for its raw columns of the (32+2r) x (8+2r) tile, a
+// register ring of the last 2r+1 weights and their running sum over z; the
+// sums go to LDS, an x-pass sums 2r+1 columns, and each output thread sums
+// 2r+1 rows.  Weights are below 2^32 (-p log2 p <= 0.531 in 2^-32 fixed point)
+// and at most 729 of them are added, so the fp64 sums are exact integers.
+template <int R, typename T>
+__global__ __launch_bounds__(kWThreads) void entropy_box(const T* __restrict__ in,
+                                                         T* __restrict__ out, Geom g, int zs,
+                                                         int tiles_x, int tiles_y, int total,
+                                                         int64_t param,
+                                                         const int64_t* __restrict__ weights,
+                                                         uint32_t gate)
+{
+    constexpr int M = 2 * R + 1;
+    constexpr int LX = kWX + 2 * R, LY = kWY + 2 * R, NRAW = LX * LY;
+    constexpr int NZ = (NRAW + kWThreads - 1) / kWThreads;
+    constexpr int XS = 8, NXS = kWX / XS, XW = XS + 2 * R, XW2 = (XW + 1) / 2 * 2;
+    constexpr int ZP = (NXS - 1) * XS + XW2 > LX ? (NXS - 1) * XS + XW2 : LX;  // even
+    static_assert(LY * NXS <= kWThreads && ZP % 2 == 0, "entropy tile shape");
+    __shared__ __align__(16) double zsum[LY * ZP + 2];
+    __shared__ __align__(16) double xsum[LY * kWX];
+
+    const int tile = xcd_tile(blockIdx.x, total);
+    const int bx = tile % tiles_x;
+    const int rest = tile / tiles_x;
+    const int by = rest % tiles_y;
+    const int bz = rest / tiles_y;
+    const int x0 = bx * kWX, y0 = by * kWY, z0 = bz * zs, z1 = min(z0 + zs, g.nz);
+    const int tid = threadIdx.x;
+    const size_t plane = (size_t)g.nx * g.ny;
+    const uint32_t pbytes = (uint32_t)(plane * sizeof(T));
+    const uint32_t* w32 = reinterpret_cast<const uint32_t*>(weights);  // low halves
+
+    uint32_t off[NZ];
+    int zi[NZ];
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) {
+        const int e = min(tid + i * kWThreads, NRAW - 1);
+        const int row = e / LX, col = e - row * LX;
+        off[i] = (uint32_t)(clampi(y0 - R + row, 0, g.ny - 1) * g.nx +
+                            clampi(x0 - R + col, 0, g.nx - 1)) * (uint32_t)sizeof(T);
+        zi[i] = row * ZP + col;
+    }
+    const bool zlast = tid + (NZ - 1) * kWThreads < NRAW;
+    auto wload = [&](uint32_t(&w)[NZ], int zsl) {
+        const rsrc_t rs = make_rsrc(in + (size_t)clampi(zsl, 0, g.nz - 1) * plane, pbytes);
+        uint32_t v[NZ];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) v[i] = buffer_load<T>(rs, off[i]);
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) w[i] = w32[2 * v[i]];
+    };
+    const int ox = tid % kWX, oy = tid / kWX;
+    const int x = x0 + ox, y = y0 + oy;
+    const uint32_t soff = (x < g.nx && y < g.ny) ? (uint32_t)(y * g.nx + x) * (uint32_t)sizeof(T)
+                                                 : pbytes;
+    const int xrow = tid % LY, xseg = tid / LY;  // x-pass: consecutive lanes, consecutive rows
+
+    // ring of the last 2r+1 weights per column and their sum, for slice z0-1
+    uint32_t ring[M][NZ];
+    double zw[NZ];
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) zw[i] = 0.0;
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+        wload(ring[u], z0 - 1 - R + u);  // slot u holds slice z0-1-r+u
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) zw[i] += (double)ring[u][i];
+    }
+    uint32_t wn[NZ];
+    wload(wn, z0 + R);
+    for (int zb = z0; zb < z1; zb += M) {
+#pragma unroll
+        for (int u = 0; u < M; ++u) {
+            const int z = zb + u;
+            if (z >= z1) break;
+            // slice z+r enters, slice z-r-1 (ring slot u) leaves
+#pragma unroll
+            for (int i = 0; i < NZ; ++i) {
+                zw[i] += (double)wn[i] - (double)ring[u][i];
+                ring[u][i] = wn[i];
+                if (i < NZ - 1 || zlast) zsum[zi[i]] = zw[i];
+            }
+            wload(wn, z + 1 + R);
+            const T p0 = in[(size_t)clampi(z, 0, g.nz - 1) * plane +
+                            (size_t)clampi(y, 0, g.ny - 1) * g.nx + clampi(x, 0, g.nx - 1)];
+            barrier_lds();
+            if (xseg < NXS) {
+                const double* rp = zsum + xrow * ZP + xseg * XS;
+                double c[XW2];
+#pragma unroll
+                for (int i = 0; i < XW2; i += 2) {
+                    const double2 t = *reinterpret_cast<const double2*>(rp + i);
+                    c[i] = t.x;
+                    c[i + 1] = t.y;
+                }
+#pragma unroll
+                for (int i = 1; i < XW; ++i) c[i] += c[i - 1];
+                double* dp = xsum + xrow * kWX + xseg * XS;
+#pragma unroll
+                for (int m = 0; m < XS; m += 2)
+                    *reinterpret_cast<double2*>(dp + m) = make_double2(
+                        c[m + 2 * R] - (m ? c[m - 1] : 0.0), c[m + 1 + 2 * R] - c[m]);
+            }
+            barrier_lds();
+            double h = 0.0;
+#pragma unroll
+            for (int t = 0; t < M; ++t) h += xsum[(oy + t) * kWX + ox];
+            uint32_t o = h > (double)param ? (uint32_t)p0 : 0u;
+            if (o < gate) o = 0;
+            const rsrc_t wr = make_rsrc(out + (size_t)z * plane, pbytes);
+            buffer_store<T>(o, wr, soff, 0);
+        }
+    }
+}
+
 template <int R, typename T, int KIND>
 hipError_t launch_win(const void* in, void* out, Geom g, int64_t param, const int64_t* weights,
                       uint32_t gate, hipStream_t s)
 {
-    const auto kern = window_planes<R, T, KIND>;
+    const auto kern = KIND == kWinEntropy ? entropy_box<R, T> : window_planes<R, T, KIND>;
     const int tiles_x = (g.nx + kWX - 1) / kWX, tiles_y = (g.ny + kWY - 1) / kWY;
     const int zs = default_zs(tiles_x * tiles_y, g.nz, resident_groups((const void*)kern, 256));
     const int total = tiles_x * tiles_y * ((g.nz + zs - 1) / zs);

@@ -102,3 +102,12 @@ def test_comparison_bad_arguments():
         assert _lib.lnf_filter_entropy(f.handle, v, dims, _lib.LNF_U16, 1, float("nan"), o) == \
             _lib.LNF_EINVAL
         assert _lib.lnf_filter_sigma(f.handle, v, dims, _lib.LNF_U16, 5, 1, o)[0] == _lib.LNF_EINVAL
+
+
+def test_entropy_filter_z_strips():
+    """A volume deep enough for several z-strips: each strip restarts the
+    running z-sums of the separable entropy kernel."""
+    v = ph.ct_u12((37, 21, 70), seed=2950)
+    with _filter() as f:
+        for r in (2, 3):
+            _same(f.entropy(_dev(v), r, 2.5), compare.entropy_filter(v, r, 2.5), f"entropy r={r}")
