@@ -2,11 +2,13 @@
 // workloads beside the nine-cluster filter:
 //   - mean (eq. 4): the box term of the MEAN9 streaming tile (mean9.hip,
 //     launch_box_mean);
-//   - sigma (eq. 5), Okada (eq. 6), entropy (eq. 7): data-dependent window
-//     filters, computed here by a direct window kernel.  A workgroup streams a
-//     32 x 8 output column down z with an LDS ring of the last 2r+1 raw planes
-//     ((32+2r) x (8+2r) voxels each); every thread evaluates one output voxel
-//     per slice from the ring.
+//   - sigma (eq. 5), Okada (eq. 6): data-dependent window filters, computed
+//     by a direct window kernel.  A workgroup streams a 32 x 8 output column
+//     down z with an LDS ring of the last 2r+1 raw planes ((32+2r) x (8+2r)
+//     voxels each); every thread evaluates one output voxel per slice from
+//     the ring;
+//   - entropy (eq. 7): the window sum of per-voxel weights is a box sum, run
+//     separably (entropy_box).
 // Readings of the formulas (garbled or silent in the paper) follow the
 // declarations in include/lnf.h.
 #include <hip/hip_runtime.h>
@@ -36,13 +38,11 @@ __global__ __launch_bounds__(kWThreads) void window_planes(const T* __restrict__
 {
     constexpr int LX = kWX + 2 * R, LY = kWY + 2 * R, NPL = 2 * R + 1;
     constexpr int NRAW = LX * LY, NLOAD = (NRAW + kWThreads - 1) / kWThreads;
-    constexpr bool ENT = KIND == kWinEntropy;
+    static_assert(KIND == kWinSigma || KIND == kWinOkada, "entropy runs on entropy_box");
     // planes of the window loop unrolled only at r = 1: a fully unrolled
     // (2r+1)^3 window hoists all its LDS reads (266 VGPRs at r = 3)
     constexpr int UZ = R <= 1 ? NPL : 1;
-    constexpr int UY = R <= 2 ? NPL : 1;  // entropy rows (64-bit weights) likewise beyond r = 2
     __shared__ uint32_t raw[NPL][NRAW];
-    __shared__ int64_t wts[ENT ? NPL : 1][ENT ? NRAW : 1];
 
     const int tile = xcd_tile(blockIdx.x, total);
     const int bx = tile % tiles_x;
@@ -77,10 +77,7 @@ __global__ __launch_bounds__(kWThreads) void window_planes(const T* __restrict__
 #pragma unroll
         for (int i = 0; i < NLOAD; ++i) {
             const int e = tid + i * kWThreads;
-            if (e < NRAW) {
-                raw[slot][e] = v[i];
-                if constexpr (ENT) wts[slot][e] = weights[v[i]];
-            }
+            if (e < NRAW) raw[slot][e] = v[i];
         }
         if (k + 1 < ns) load(z0 - R + k + 1);
         barrier_lds();
@@ -128,17 +125,6 @@ __global__ __launch_bounds__(kWThreads) void window_planes(const T* __restrict__
                 // (2 sum + cnt) / (2 cnt) < 2^27 / 2: its fp64 quotient never
                 // rounds across an integer, so truncation is the exact floor
                 o = (uint32_t)((double)(2 * sum + cnt) / (double)(2 * cnt));
-            } else {
-                int64_t h = 0;
-#pragma unroll UZ
-                for (int dz = 0; dz < NPL; ++dz) {
-                    const int64_t* pl = wts[(k - 2 * R + dz) % NPL];
-#pragma unroll UY
-                    for (int dy = 0; dy <= 2 * R; ++dy)
-#pragma unroll
-                        for (int dx = 0; dx <= 2 * R; ++dx) h += pl[(oy + dy) * LX + ox + dx];
-                }
-                o = h > param ? p0 : 0u;
             }
             if (o < gate) o = 0;
             const int x = x0 + ox, y = y0 + oy;
@@ -273,7 +259,10 @@ template <int R, typename T, int KIND>
 hipError_t launch_win(const void* in, void* out, Geom g, int64_t param, const int64_t* weights,
                       uint32_t gate, hipStream_t s)
 {
-    const auto kern = KIND == kWinEntropy ? entropy_box<R, T> : window_planes<R, T, KIND>;
+    const auto kern = [] {
+        if constexpr (KIND == kWinEntropy) return entropy_box<R, T>;
+        else return window_planes<R, T, KIND>;
+    }();
     const int tiles_x = (g.nx + kWX - 1) / kWX, tiles_y = (g.ny + kWY - 1) / kWY;
     const int zs = default_zs(tiles_x * tiles_y, g.nz, resident_groups((const void*)kern, 256));
     const int total = tiles_x * tiles_y * ((g.nz + zs - 1) / zs);
