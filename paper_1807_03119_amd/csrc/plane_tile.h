@@ -144,20 +144,26 @@ struct PTSmem {
     using QT = std::conditional_t<sizeof(T) == 1, uint32_t, double>;
     static constexpr bool VAR = S::VAR, CROSS = S::CROSS;
     static constexpr bool WIDE = sizeof(QT) == 8;
+    // MINVAR9 centre entries as one 64-bit key v * 2^16 + rounded mean, when
+    // every v fits 48 bits: v = n^2 times a variance of values in [0, vmax],
+    // so v <= n^2 vmax^2 / 4 (uint16 cubes up to r = 3, crosses, all uint8)
+    static constexpr double VMAX = sizeof(T) == 1 ? 255.0 : 65535.0;
+    static constexpr bool PACK =
+        VAR && (double)S::N * S::N * VMAX * VMAX / 4.0 < 281474976710656.0;  // 2^48
     static constexpr int XPQ = WIDE ? S::XPD : S::XPB;
     // every array a multiple of 16 bytes, so each starts 16-byte aligned
     static constexpr int a16(int n, int bytes) { return (n * bytes + 15) / 16 * 16 / bytes; }
     static constexpr int QN = VAR ? 1 : 0, CN = CROSS ? 1 : 0;
     QT xq[QN ? a16(S::XROWS * XPQ, sizeof(QT)) : a16(1, sizeof(QT))];
     QT yq[QN * CN ? a16(S::XROWS * XPQ, sizeof(QT)) : a16(1, sizeof(QT))];  // crosses: y-lines of E^2
-    double vv[QN ? a16(S::GY * S::VP, 8) : 2];
+    double vv[QN ? a16(S::GY * S::VP, 8) : 2];   // MINVAR9: v, or the packed keys
     uint32_t zb[S::ZN];
     uint32_t zq0[QN ? S::ZN : 4];                // uint8: Zq; uint16: low half of Zq
     uint32_t zq1[QN && WIDE ? S::ZN : 4];        // uint16: high half of Zq
     uint32_t ec[CN ? S::ZN : 4];                 // crosses: slice p
     uint32_t xb[a16(S::XROWS * S::XPB, 4)];      // cubes: x-pass; crosses: x-lines
     uint32_t yb[CN ? a16(S::XROWS * S::XPB, 4) : 4];  // crosses: y-lines
-    uint32_t vo[a16(S::GY * S::VP, 4)];          // MINVAR9: rounded means; MEAN9: B
+    uint32_t vo[PACK ? 4 : a16(S::GY * S::VP, 4)];  // MINVAR9: rounded means; MEAN9: B
 };
 
 // dn = n; inv = 1/n (MINVAR9) or 1/(9n) (MEAN9).
@@ -170,7 +176,7 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T>& sm,
     using S = PTShape<R, D, SHAPE, RULE>;
     using SM = PTSmem<R, D, SHAPE, RULE, T>;
     using QT = typename SM::QT;
-    constexpr bool VAR = S::VAR, CROSS = S::CROSS, WIDE = SM::WIDE;
+    constexpr bool VAR = S::VAR, CROSS = S::CROSS, WIDE = SM::WIDE, PACK = SM::PACK;
     static_assert(offsetof(SM, vv) % 16 == 0 && offsetof(SM, zb) % 16 == 0 &&
                       offsetof(SM, zq0) % 16 == 0 && offsetof(SM, zq1) % 16 == 0 &&
                       offsetof(SM, ec) % 16 == 0 && offsetof(SM, xb) % 16 == 0 &&
@@ -243,13 +249,17 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T>& sm,
     // mean) of the best so far, MEAN9 partial sums
     double av[U][OPT], mv[U][OPT];
     uint32_t ao[U][OPT], mo[U][OPT];
+    uint64_t ak[U][OPT], mk[U][OPT];  // packed keys
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int j = 0; j < OPT; ++j) {
             av[u][j] = mv[u][j] = 0.0;
             ao[u][j] = mo[u][j] = 0;
+            ak[u][j] = mk[u][j] = 0;
         }
+    uint64_t* const keys = reinterpret_cast<uint64_t*>(sm.vv);
+    constexpr uint64_t kHigh = ~0xffffull;  // a key's v part (key & kHigh = v * 2^16)
 
     // y-pass mapping: consecutive lanes take consecutive centre columns
     const int ycol = tid % GX, yseg = tid / GX;
@@ -320,7 +330,13 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T>& sm,
 
     // the centre statistics of one centre: MINVAR9 (v, rounded mean), MEAN9 B
     auto centre_out = [&](int gy, int gx, uint32_t b, QT qv) {
-        if constexpr (VAR) {
+        if constexpr (PACK) {
+            // v + 2^52 is exact (v < 2^48), so its mantissa field is v
+            const double db = (double)b;
+            const double vb = __builtin_fma(dn, (double)qv, __builtin_fma(-db, db, 0x1p52));
+            const uint64_t v = __builtin_bit_cast(uint64_t, vb) & ((1ull << 52) - 1);
+            keys[gy * VP + gx] = (v << 16) | round_div_odd(b, inv);
+        } else if constexpr (VAR) {
             const double db = (double)b;
             sm.vv[gy * VP + gx] = __builtin_fma(dn, (double)qv, -db * db);
             sm.vo[gy * VP + gx] = round_div_odd(b, inv);
@@ -458,7 +474,21 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T>& sm,
                 const int oy = oyb + j * S::OROWS;
                 const int ic = (oy + D) * VP + ox + D;
                 uint32_t o;
-                if constexpr (VAR) {
+                if constexpr (PACK) {
+                    // c.v < b.v  <=>  c.key < (b.key & kHigh): the same
+                    // first minima as the unpacked branch below
+                    const uint64_t ck = keys[ic];
+                    uint64_t gk = keys[oy * VP + ox];
+#pragma unroll
+                    for (int k = 1; k < 4; ++k) {
+                        const int ik = (oy + ((k & 2) ? 2 * D : 0)) * VP + ox + ((k & 1) ? 2 * D : 0);
+                        const uint64_t kk = keys[ik];
+                        gk = kk < (gk & kHigh) ? kk : gk;
+                    }
+                    o = (uint32_t)(gk < (mk[ur][j] & kHigh) ? gk : mk[ur][j]) & 0xffffu;
+                    mk[u][j] = ak[ur][j] < (ck & kHigh) ? ak[ur][j] : ck;
+                    ak[u][j] = gk;
+                } else if constexpr (VAR) {
                     const double cv = sm.vv[ic];
                     const uint32_t co = sm.vo[ic];
                     double gv = sm.vv[oy * VP + ox];
