@@ -130,9 +130,10 @@ struct PTShape {
     static constexpr int OPT = TX * TY / THREADS;         // outputs per thread
     static constexpr int OROWS = THREADS / TX;            // output rows per pass
     static constexpr int U = D + 1;                       // register ring period
-    // waves per SIMD the kernels are compiled for: 3 for MINVAR9 cubes at
-    // offset r up to r = 3 (fits without spills), else no limit below 256 VGPRs
-    static constexpr int WAVES = (VAR && !CROSS && D == R && R <= 3) ? 3 : 2;
+    // waves per SIMD the kernels are compiled for: 4 for MINVAR9 cubes at
+    // offset r up to r = 3 (128 VGPRs; at r = 3 uint16 with a few spills,
+    // still 6 % faster than 3 waves), else no limit below 256 VGPRs
+    static constexpr int WAVES = (VAR && !CROSS && D == R && R <= 3) ? 4 : 2;
     static_assert(THREADS % TX == 0 && OPT * OROWS == TY, "gather mapping");
 };
 
