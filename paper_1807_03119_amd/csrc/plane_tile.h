@@ -131,8 +131,8 @@ struct PTShape {
     static constexpr int OROWS = THREADS / TX;            // output rows per pass
     static constexpr int U = D + 1;                       // register ring period
     // waves per SIMD the kernels are compiled for: 4 for MINVAR9 cubes at
-    // offset r up to r = 3 (128 VGPRs; at r = 3 uint16 with a few spills,
-    // still 6 % faster than 3 waves), else no limit below 256 VGPRs
+    // offset r up to r = 3 (at most 128 VGPRs, no spills), else no limit
+    // below 256 VGPRs
     static constexpr int WAVES = (VAR && !CROSS && D == R && R <= 3) ? 4 : 2;
     static_assert(THREADS % TX == 0 && OPT * OROWS == TY, "gather mapping");
 };
@@ -276,8 +276,10 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T>& sm,
             if (xrow >= S::XIN) continue;
             const int cbase = xseg * XS;
             const int zr = (S::XROW0 + xrow) * S::ZP + cbase;
-            uint32_t wb[S::XW4], w0[S::XW4], w1[S::XW4];
-            auto read_row = [&](const uint32_t* a, uint32_t(&w)[S::XW4]) {
+            // sums first, then squares: one row segment live at a time keeps
+            // the x-pass within the 4-waves-per-SIMD register budget
+            uint32_t w[S::XW4];
+            auto read_row = [&](const uint32_t* a) {
 #pragma unroll
                 for (int i = 0; i < S::XW4; i += 4) {
                     const uint4 t = *reinterpret_cast<const uint4*>(a + zr + i);
@@ -287,39 +289,47 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T>& sm,
                     w[i + 3] = t.w;
                 }
             };
-            read_row(src, wb);
-            if constexpr (VAR && !CROSS) {
-                read_row(src0, w0);
-                if constexpr (WIDE) read_row(src1, w1);
-            }
-            auto wq = [&](int i) -> QT {
-                if constexpr (CROSS) return sq(wb[i]);
-                else if constexpr (WIDE)
-                    return __builtin_bit_cast(double, ((uint64_t)w1[i] << 32) | w0[i]);
-                else return w0[i];
-            };
-            uint32_t cb[S::XW];
-            QT cq[S::XW];
-            cb[0] = wb[0];
-            if constexpr (VAR) cq[0] = wq(0);
-#pragma unroll
-            for (int i = 1; i < S::XW; ++i) {
-                cb[i] = cb[i - 1] + wb[i];
-                if constexpr (VAR) cq[i] = cq[i - 1] + wq(i);
-            }
-            uint32_t ob[XS];
-            QT oq[XS];
-#pragma unroll
-            for (int m = 0; m < XS; ++m) {
-                ob[m] = cb[m + 2 * R] - (m ? cb[m - 1] : 0u);
-                if constexpr (VAR) oq[m] = cq[m + 2 * R] - (m ? cq[m - 1] : (QT)0);
-            }
             uint32_t* db = sm.xb + xrow * S::XPB + cbase;
             QT* dq = sm.xq + xrow * SM::XPQ + cbase;
+            read_row(src);
+            {
+                uint32_t cb[S::XW];
+                cb[0] = w[0];
 #pragma unroll
-            for (int m = 0; m < XS; m += 2) {
-                *reinterpret_cast<uint2*>(db + m) = make_uint2(ob[m], ob[m + 1]);
-                if constexpr (VAR) {
+                for (int i = 1; i < S::XW; ++i) cb[i] = cb[i - 1] + w[i];
+                uint32_t ob[XS];
+#pragma unroll
+                for (int m = 0; m < XS; ++m) ob[m] = cb[m + 2 * R] - (m ? cb[m - 1] : 0u);
+#pragma unroll
+                for (int m = 0; m < XS; m += 2)
+                    *reinterpret_cast<uint2*>(db + m) = make_uint2(ob[m], ob[m + 1]);
+            }
+            if constexpr (VAR) {
+                QT cq[S::XW];
+                if constexpr (CROSS) {  // squares of the raw row just read
+#pragma unroll
+                    for (int i = 0; i < S::XW; ++i) cq[i] = sq(w[i]);
+                } else if constexpr (WIDE) {  // Zq from its two 32-bit halves
+                    uint32_t lo[S::XW4];
+                    read_row(src0);
+#pragma unroll
+                    for (int i = 0; i < S::XW4; ++i) lo[i] = w[i];
+                    read_row(src1);
+#pragma unroll
+                    for (int i = 0; i < S::XW; ++i)
+                        cq[i] = __builtin_bit_cast(double, ((uint64_t)w[i] << 32) | lo[i]);
+                } else {
+                    read_row(src0);
+#pragma unroll
+                    for (int i = 0; i < S::XW; ++i) cq[i] = w[i];
+                }
+#pragma unroll
+                for (int i = 1; i < S::XW; ++i) cq[i] += cq[i - 1];
+                QT oq[XS];
+#pragma unroll
+                for (int m = 0; m < XS; ++m) oq[m] = cq[m + 2 * R] - (m ? cq[m - 1] : (QT)0);
+#pragma unroll
+                for (int m = 0; m < XS; m += 2) {
                     if constexpr (WIDE)
                         *reinterpret_cast<double2*>(dq + m) = make_double2(oq[m], oq[m + 1]);
                     else
