@@ -266,10 +266,11 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T>& sm,
     const int ycol = tid % GX, yseg = tid / GX;
     const bool yact = yseg < S::NYS;
 
-    // x-pass over the 32-bit array `src` (and `srcq` for the squares): row
-    // segments of raw rows XROW0 + row, box sums over 2r+1 columns for the
-    // centre columns, written to xb (and xq) at x-pass row `row`.  Crosses
-    // square the raw values (srcq unused); cubes read Zq (two halves if WIDE).
+    // x-pass over the 32-bit array `src`: row segments of raw rows XROW0 +
+    // row, box sums over 2r+1 columns for the centre columns, written to xb at
+    // x-pass row `row`; for MINVAR9 the same for the squares, written to xq.
+    // Crosses square the raw values of `src`; cubes read Zq from `src0` (low
+    // halves, or the uint32 sums) and `src1` (high halves, uint16 data).
     auto xpass = [&](const uint32_t* src, const uint32_t* src0, const uint32_t* src1) {
         for (int it = tid; it < S::NXI; it += kT) {
             const int xrow = it % S::XR, xseg = it / S::XR;
