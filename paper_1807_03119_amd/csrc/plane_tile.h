@@ -86,7 +86,9 @@ struct PTShape {
     static constexpr bool CROSS = SHAPE == kClusterCross;
     static constexpr bool VAR = RULE == kRuleMinVar9;
     static constexpr int THREADS = 256;
-    static constexpr int TX = 32, TY = D <= R ? 16 : 8;
+    // 16 output rows, except where a deep ring (D > r) of MINVAR9 entries
+    // would push registers past about 200: crosses from r = 3, every r = 4
+    static constexpr int TX = 32, TY = (D <= R || !VAR || R <= 2 || (R == 3 && !CROSS)) ? 16 : 8;
     static constexpr int M = 2 * R + 1;
     static constexpr int N = CROSS ? 3 * M : M * M * M;   // voxels per cluster
     static constexpr int E = D + R;                       // raw halo
