@@ -92,13 +92,21 @@ __global__ __launch_bounds__(kWThreads) void window_planes(const T* __restrict__
                 const uint32_t nb[7] = {p0, raw[cslot][c - 1], raw[cslot][c + 1],
                                         raw[cslot][c - LX], raw[cslot][c + LX],
                                         raw[(k - 2) % NPL][c], raw[k % NPL][c]};
+                // |w - p0| < param  <=>  lo <= w <= hi with lo = p0 - param + 1,
+                // hi = p0 + param - 1, tested as (w - lo) <= hi - lo; no value
+                // passes when param <= 0
                 uint32_t sum = 0, cnt = 0;
+                if (param > 0) {
+                    const int64_t lo64 = (int64_t)p0 - param + 1;
+                    const uint64_t hi64 = (uint64_t)p0 + (uint64_t)param - 1;
+                    const uint32_t lo = lo64 > 0 ? (uint32_t)lo64 : 0u;
+                    const uint32_t span =
+                        (uint32_t)(hi64 < 0xffffffffull ? hi64 : 0xffffffffull) - lo;
 #pragma unroll
-                for (int i = 0; i < 7; ++i) {
-                    const uint32_t d = nb[i] > p0 ? nb[i] - p0 : p0 - nb[i];
-                    if ((int64_t)d < param) {
-                        sum += nb[i];
-                        cnt += 1;
+                    for (int i = 0; i < 7; ++i) {
+                        const bool in = nb[i] - lo <= span;
+                        sum += in ? nb[i] : 0u;
+                        cnt += in ? 1u : 0u;
                     }
                 }
                 o = cnt ? (uint32_t)((double)(2 * sum + cnt) / (double)(2 * cnt)) : 0u;
