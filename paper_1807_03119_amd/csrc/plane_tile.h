@@ -132,10 +132,11 @@ struct PTShape {
     static constexpr int OPT = TX * TY / THREADS;         // outputs per thread
     static constexpr int OROWS = THREADS / TX;            // output rows per pass
     static constexpr int U = D + 1;                       // register ring period
-    // waves per SIMD the kernels are compiled for: 4 for MINVAR9 cubes at
-    // offset r up to r = 3 (at most 128 VGPRs, no spills), else no limit
-    // below 256 VGPRs
-    static constexpr int WAVES = (VAR && !CROSS && D == R && R <= 3) ? 4 : 2;
+    // waves per SIMD the kernels are compiled for: MINVAR9 cubes at offset r
+    // get 4 up to r = 3 (at most 128 VGPRs, no spills) and 3 at r = 4 (168
+    // VGPRs; a few spills for uint16, still 13 % faster than 2 waves); the
+    // others have no limit below 256 VGPRs
+    static constexpr int WAVES = (VAR && !CROSS && D == R) ? (R <= 3 ? 4 : 3) : 2;
     static_assert(THREADS % TX == 0 && OPT * OROWS == TY, "gather mapping");
 };
 
