@@ -315,7 +315,7 @@ int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>
                           : mean9_default_variant(dtype, r);
             mean9_tile_shape(variant, &tx, &ty);
         } else {
-            minvar9_tile_shape(0, &tx, &ty);
+            minvar9_tile_shape(0, r, &tx, &ty);
         }
         kern[c] = class_kernel(h->rule, c, h->gate != 0, variant);
         // z-strips: the class's volumes differ in depth, so its workgroups

@@ -12,7 +12,7 @@ namespace {
 
 // The gate is a runtime value here (0 = off): one instantiation per geometry.
 template <int R, int D, int SHAPE, int RULE, typename T>
-__global__ __launch_bounds__(256)
+__global__ __launch_bounds__((PTShape<R, D, SHAPE, RULE>::THREADS))
 __attribute__((amdgpu_waves_per_eu(PTShape<R, D, SHAPE, RULE>::WAVES))) void cluster_planes(
     const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
     int total, uint32_t gate, double dn, double inv)
@@ -33,7 +33,6 @@ template <int R, int D, int SHAPE, int RULE, typename T>
 hipError_t launch_geom(const void* in, void* out, Geom g, uint32_t gate, int zs, hipStream_t s)
 {
     using S = PTShape<R, D, SHAPE, RULE>;
-    static_assert(S::THREADS == 256, "launch shape");
     const auto kern = cluster_planes<R, D, SHAPE, RULE, T>;
     const int tiles_x = (g.nx + S::TX - 1) / S::TX, tiles_y = (g.ny + S::TY - 1) / S::TY;
     if (zs <= 0)

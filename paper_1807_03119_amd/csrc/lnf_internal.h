@@ -50,7 +50,7 @@ hipError_t launch_window(int kind, const void* in, void* out, int dtype, int r, 
 
 // ---- MINVAR9 (least-variance cluster) -------------------------------------
 int minvar9_variants();
-void minvar9_tile_shape(int variant, int* tx, int* ty);
+void minvar9_tile_shape(int variant, int r, int* tx, int* ty);  // output tile of (variant, r)
 hipError_t launch_minvar9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
                           TileCfg cfg, hipStream_t s);
 

@@ -7,68 +7,86 @@
 namespace lnf {
 namespace {
 
-template <int R, typename T, bool GATE>
-__global__ __launch_bounds__(MV9Shape<R>::THREADS)
-__attribute__((amdgpu_waves_per_eu(MV9Shape<R>::WAVES))) void minvar9_planes(const T* __restrict__ in, T* __restrict__ out,
-                                                      Geom g, int zs, int tiles_x, int tiles_y,
-                                                      int total, uint32_t gate, double dn,
-                                                      double invn)
+template <int R, typename T, bool GATE, bool WT>
+__global__ __launch_bounds__((MV9Shape<R, WT>::THREADS))
+__attribute__((amdgpu_waves_per_eu(MV9Shape<R, WT>::WAVES))) void minvar9_planes(
+    const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
+    int total, uint32_t gate, double dn, double invn)
 {
-    __shared__ __align__(16) MV9Smem<R, T> sm;
+    using S = MV9Shape<R, WT>;
+    __shared__ __align__(16) MV9Smem<R, T, WT> sm;
     const int tile = xcd_tile(blockIdx.x, total);
     const int bx = tile % tiles_x;
     const int rest = tile / tiles_x;
     const int by = rest % tiles_y;
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
-    minvar9_tile<R, T, GATE>(sm, in, out, g, bx * MV9Shape<R>::TX, by * MV9Shape<R>::TY, z0,
-                             min(z0 + zs, g.nz), gate, dn, invn);
+    minvar9_tile<R, T, GATE, WT>(sm, in, out, g, bx * S::TX, by * S::TY, z0, min(z0 + zs, g.nz),
+                                 gate, dn, invn);
 }
 
-template <int R, typename T>
+template <int R, typename T, bool WT>
 hipError_t launch_planes(const void* in, void* out, Geom g, uint32_t gate, int zs, hipStream_t s)
 {
-    using S = MV9Shape<R>;
+    using S = MV9Shape<R, WT>;
     const int tiles_x = (g.nx + S::TX - 1) / S::TX, tiles_y = (g.ny + S::TY - 1) / S::TY;
     if (zs <= 0)
         zs = default_zs(tiles_x * tiles_y, g.nz,
-                        resident_groups((const void*)minvar9_planes<R, T, false>, S::THREADS));
+                        resident_groups((const void*)minvar9_planes<R, T, false, WT>, S::THREADS));
     const int nzs = (g.nz + zs - 1) / zs;
     const int total = tiles_x * tiles_y * nzs;
     const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
     const T* pin = static_cast<const T*>(in);
     T* pout = static_cast<T*>(out);
     if (gate)
-        hipLaunchKernelGGL((minvar9_planes<R, T, true>), dim3(total), dim3(S::THREADS), 0, s,
+        hipLaunchKernelGGL((minvar9_planes<R, T, true, WT>), dim3(total), dim3(S::THREADS), 0, s,
                            pin, pout, g, zs, tiles_x, tiles_y, total, gate, (double)n, 1.0 / n);
     else
-        hipLaunchKernelGGL((minvar9_planes<R, T, false>), dim3(total), dim3(S::THREADS), 0, s,
+        hipLaunchKernelGGL((minvar9_planes<R, T, false, WT>), dim3(total), dim3(S::THREADS), 0, s,
                            pin, pout, g, zs, tiles_x, tiles_y, total, gate, (double)n, 1.0 / n);
     return hipGetLastError();
+}
+
+template <int R, typename T>
+hipError_t launch_variant(int variant, const void* in, void* out, Geom g, uint32_t gate, int zs,
+                          hipStream_t s)
+{
+    if (variant == 1) return launch_planes<R, T, true>(in, out, g, gate, zs, s);
+    return launch_planes<R, T, false>(in, out, g, gate, zs, s);
 }
 
 template <typename T>
 hipError_t dispatch_r(const void* in, void* out, int r, Geom g, uint32_t gate, TileCfg cfg,
                       hipStream_t s)
 {
+    // default variant: the wide tile for uint16 at r = 3 on large planes
+    // (where it measured faster), else 32 x 16
+    int v = cfg.variant;
+    if (v < 0) v = (sizeof(T) == 2 && r == 3 && g.nx >= 256 && g.ny >= 256) ? 1 : 0;
     switch (r) {
-    case 1: return launch_planes<1, T>(in, out, g, gate, cfg.zs, s);
-    case 2: return launch_planes<2, T>(in, out, g, gate, cfg.zs, s);
-    case 3: return launch_planes<3, T>(in, out, g, gate, cfg.zs, s);
-    case 4: return launch_planes<4, T>(in, out, g, gate, cfg.zs, s);
+    case 1: return launch_variant<1, T>(v, in, out, g, gate, cfg.zs, s);
+    case 2: return launch_variant<2, T>(v, in, out, g, gate, cfg.zs, s);
+    case 3: return launch_variant<3, T>(v, in, out, g, gate, cfg.zs, s);
+    case 4: return launch_variant<4, T>(v, in, out, g, gate, cfg.zs, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-int minvar9_variants() { return 1; }
+// 0: 32 x 16 outputs, 256 threads; 1: 64 x 16 outputs, 512 threads (up to
+// r = 3; the same tile as 0 at r = 4)
+int minvar9_variants() { return 2; }
 
-void minvar9_tile_shape(int variant, int* tx, int* ty)
+void minvar9_tile_shape(int variant, int r, int* tx, int* ty)
 {
-    (void)variant;
-    *tx = MV9Shape<1>::TX;  // one tile shape for every radius
-    *ty = MV9Shape<1>::TY;
+    const bool w = variant == 1;
+    switch (r) {
+    case 1: *tx = w ? MV9Shape<1, true>::TX : MV9Shape<1>::TX; *ty = MV9Shape<1>::TY; return;
+    case 2: *tx = w ? MV9Shape<2, true>::TX : MV9Shape<2>::TX; *ty = MV9Shape<2>::TY; return;
+    case 3: *tx = w ? MV9Shape<3, true>::TX : MV9Shape<3>::TX; *ty = MV9Shape<3>::TY; return;
+    default: *tx = MV9Shape<4>::TX; *ty = MV9Shape<4>::TY; return;
+    }
 }
 
 hipError_t launch_minvar9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,

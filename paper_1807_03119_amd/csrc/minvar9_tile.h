@@ -7,19 +7,20 @@
 
 namespace lnf {
 
-template <int R>
-using MV9Shape = PTShape<R, R, kClusterBox, kRuleMinVar9>;
-template <int R, typename T>
-using MV9Smem = PTSmem<R, R, kClusterBox, kRuleMinVar9, T>;
+// WT: the wide-tile variant (64 x 16 outputs, 512 threads, up to r = 3).
+template <int R, bool WT = false>
+using MV9Shape = PTShape<R, R, kClusterBox, kRuleMinVar9, WT>;
+template <int R, typename T, bool WT = false>
+using MV9Smem = PTSmem<R, R, kClusterBox, kRuleMinVar9, T, WT>;
 
 // dn = n, invn = 1/n.
-template <int R, typename T, bool GATE>
-__device__ __forceinline__ void minvar9_tile(MV9Smem<R, T>& sm, const T* __restrict__ in,
+template <int R, typename T, bool GATE, bool WT = false>
+__device__ __forceinline__ void minvar9_tile(MV9Smem<R, T, WT>& sm, const T* __restrict__ in,
                                              T* __restrict__ out, Geom g, int x0, int y0, int z0,
                                              int z1, uint32_t gate, double dn, double invn)
 {
-    plane_tile<R, R, kClusterBox, kRuleMinVar9, T, GATE>(sm, in, out, g, x0, y0, z0, z1, gate, dn,
-                                                         invn);
+    plane_tile<R, R, kClusterBox, kRuleMinVar9, T, GATE, WT>(sm, in, out, g, x0, y0, z0, z1, gate,
+                                                             dn, invn);
 }
 
 }  // namespace lnf

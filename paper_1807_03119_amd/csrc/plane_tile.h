@@ -81,14 +81,19 @@ constexpr int pt_pitch(int ys, int g, int lo, int m, bool two_mod4)
                                                       : lo + (lo & 1);
 }
 
-template <int R, int D, int SHAPE, int RULE>
+// WT (wide tile): MINVAR9 cubes at offset r up to r = 3 fit 4 waves per SIMD,
+// so 64 x 16 tiles in 512-thread workgroups cost less halo at the same
+// occupancy: faster on large uint16 planes (r = 3: 214 -> 228 Gvox/s), slower
+// on small volumes and on uint8 at r = 2.  A tile variant, chosen per launch.
+template <int R, int D, int SHAPE, int RULE, bool WT = false>
 struct PTShape {
     static constexpr bool CROSS = SHAPE == kClusterCross;
     static constexpr bool VAR = RULE == kRuleMinVar9;
-    static constexpr int THREADS = 256;
+    static constexpr bool BIG = WT && VAR && !CROSS && D == R && R <= 3;
+    static constexpr int THREADS = BIG ? 512 : 256;
     // 16 output rows, except where a deep ring (D > r) of MINVAR9 entries
     // would push registers past about 200: crosses from r = 3, every r = 4
-    static constexpr int TX = 32, TY = (D <= R || !VAR || R <= 2 || (R == 3 && !CROSS)) ? 16 : 8;
+    static constexpr int TX = BIG ? 64 : 32, TY = (D <= R || !VAR || R <= 2 || (R == 3 && !CROSS)) ? 16 : 8;
     static constexpr int M = 2 * R + 1;
     static constexpr int N = CROSS ? 3 * M : M * M * M;   // voxels per cluster
     static constexpr int E = D + R;                       // raw halo
@@ -140,9 +145,9 @@ struct PTShape {
     static_assert(THREADS % TX == 0 && OPT * OROWS == TY, "gather mapping");
 };
 
-template <int R, int D, int SHAPE, int RULE, typename T>
+template <int R, int D, int SHAPE, int RULE, typename T, bool WT = false>
 struct PTSmem {
-    using S = PTShape<R, D, SHAPE, RULE>;
+    using S = PTShape<R, D, SHAPE, RULE, WT>;
     // sums of squares: fp64 for uint16 data, staged in LDS as two 32-bit
     // halves (so they share the 32-bit layout); uint32 for uint8 data
     using QT = std::conditional_t<sizeof(T) == 1, uint32_t, double>;
@@ -171,14 +176,14 @@ struct PTSmem {
 };
 
 // dn = n; inv = 1/n (MINVAR9) or 1/(9n) (MEAN9).
-template <int R, int D, int SHAPE, int RULE, typename T, bool GATE>
-__device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T>& sm,
+template <int R, int D, int SHAPE, int RULE, typename T, bool GATE, bool WT = false>
+__device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
                                            const T* __restrict__ in, T* __restrict__ out, Geom g,
                                            int x0, int y0, int z0, int z1, uint32_t gate,
                                            double dn, double inv)
 {
-    using S = PTShape<R, D, SHAPE, RULE>;
-    using SM = PTSmem<R, D, SHAPE, RULE, T>;
+    using S = PTShape<R, D, SHAPE, RULE, WT>;
+    using SM = PTSmem<R, D, SHAPE, RULE, T, WT>;
     using QT = typename SM::QT;
     constexpr bool VAR = S::VAR, CROSS = S::CROSS, WIDE = SM::WIDE, PACK = SM::PACK;
     static_assert(offsetof(SM, vv) % 16 == 0 && offsetof(SM, zb) % 16 == 0 &&

@@ -243,6 +243,21 @@ def test_error_codes(filters):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+def test_minvar9_extreme_values_every_variant(variant):
+    """MINVAR9 at the type's extremes: variance numerators near their bound
+    (the packed 64-bit keys hold v below 2^48), both tile variants."""
+    from paper_1807_03119_amd.api import Filter
+    u16 = ph.random_volume((70, 33, 20), np.uint16, seed=5, kind="extreme")
+    u8 = ph.random_volume((45, 38, 21), np.uint8, seed=6, kind="extreme")
+    with Filter(_lib.LNF_MINVAR9, 0) as f:
+        for v in (u16, u8):
+            for r in (1, 2, 3, 4):
+                got = _gpu(f, v, r, variant=variant)
+                _assert_same(got, oracle.filter_volume(v, r, oracle.MINVAR9), v, r,
+                             f"minvar9 extremes v{variant} r={r}")
+
+
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_extreme_values_every_variant(variant):
     """Voxels at the type's extremes (0 and the maximum) give the largest
