@@ -59,10 +59,11 @@ template <typename T>
 hipError_t dispatch_r(const void* in, void* out, int r, Geom g, uint32_t gate, TileCfg cfg,
                       hipStream_t s)
 {
-    // default variant: the wide tile for uint16 at r = 3 on large planes
-    // (where it measured faster), else 32 x 16
+    // default variant: the wide tile on large planes where it measured faster
+    // (uint16 up to r = 3, uint8 at r = 3), else 32 x 16
     int v = cfg.variant;
-    if (v < 0) v = (sizeof(T) == 2 && r == 3 && g.nx >= 256 && g.ny >= 256) ? 1 : 0;
+    if (v < 0)
+        v = (g.nx >= 256 && g.ny >= 256 && r <= 3 && (sizeof(T) == 2 || r == 3)) ? 1 : 0;
     switch (r) {
     case 1: return launch_variant<1, T>(v, in, out, g, gate, cfg.zs, s);
     case 2: return launch_variant<2, T>(v, in, out, g, gate, cfg.zs, s);
