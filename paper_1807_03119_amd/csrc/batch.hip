@@ -77,7 +77,8 @@ __device__ __forceinline__ const BatchJobDesc& job_of(const BatchTable* tab, con
 }
 
 template <int R, int TY, typename T, bool GATE, int TXW>
-__global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS)) void mean9_multi(
+__global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS))
+__attribute__((amdgpu_waves_per_eu(2))) void mean9_multi(
     const BatchTable* __restrict__ tab, int cls, uint32_t gate)
 {
     __shared__ __align__(16) M9SmemAny<R, TY, TXW> sm;

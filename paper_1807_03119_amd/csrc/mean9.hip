@@ -185,8 +185,12 @@ __global__ __launch_bounds__(kThreads) void mean9_ring_64x16(const T* __restrict
 }
 
 // Single-volume wrapper around the streaming tile body of mean9_tile.h.
+// At least 2 waves per SIMD: at r = 4 the tile would take 274-285 VGPRs (one
+// wave per SIMD); capped at 256 it spills a little and still runs faster
+// (512^3, r = 4: uint16 406 -> 425, uint8 418 -> 466 Gvox/s); r <= 3 fits anyway.
 template <int R, int TY, typename T, bool GATE, int TXW>
-__global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS)) void mean9_stream(
+__global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS))
+__attribute__((amdgpu_waves_per_eu(2))) void mean9_stream(
     const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
     int total, uint32_t gate, double inv9n, int pairs)
 {
@@ -259,7 +263,7 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // Default variant per voxel type and radius (index r-1): the fastest at the
 // default z-strip depth on 512^3 volumes.
-constexpr int kDefaultU16[LNF_RADIUS_MAX] = {2, 1, 1, 3};
+constexpr int kDefaultU16[LNF_RADIUS_MAX] = {2, 1, 1, 4};
 constexpr int kDefaultU8[LNF_RADIUS_MAX] = {2, 4, 3, 3};
 
 template <int R, typename T, bool GATE, int TY, int TXW>
