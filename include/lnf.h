@@ -138,6 +138,19 @@ typedef struct {
 /* Number of compiled tile shapes for (rule, dtype, radius); < 0 on bad arguments. */
 LNF_API int lnf_tile_variants(int rule, int dtype, int radius);
 
+/*
+ * The tile configuration lnf_filter would use for a volume of these dims with
+ * this context (its rule, geometry and tuned choices): the tile variant and
+ * the z-strip depth, so that a caller can see where the z-strips of the launch
+ * start (every multiple of tile->zs).  No device work; no device memory is
+ * touched.  Geometry-variant contexts have one tile shape (variant 0).
+ *   tile  written on success.
+ * Errors: LNF_EINVAL (NULL arguments, dtype, radius, dims as lnf_filter),
+ * LNF_EHIP.
+ */
+LNF_API int lnf_tile_config(lnf_handle h, const int64_t dims[3], int dtype, int radius,
+                            lnf_tile* tile);
+
 /* lnf_filter with an explicit tile configuration (tile == NULL: as lnf_filter). */
 LNF_API int lnf_filter_tiled(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
                              int radius, void* out, hipStream_t stream, const lnf_tile* tile);

@@ -87,6 +87,7 @@ def _declare(lib):
         "lnf_filter_tiled": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, _vp, _vp,
                              ctypes.POINTER(lnf_tile)],
         "lnf_tile_variants": [_i32, _i32, _i32],
+        "lnf_tile_config": [_vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, ctypes.POINTER(lnf_tile)],
         "lnf_filter_batch": [_vp, ctypes.POINTER(lnf_job), _i32, _vp],
         "lnf_tune": [_vp, ctypes.POINTER(lnf_job), _i32],
         "lnf_tune_save": [_vp, ctypes.c_char_p],
@@ -215,6 +216,15 @@ def lnf_tile_variants(rule: int, dtype: int, radius: int) -> int:
     if n < 0:
         raise LnfError(n, "lnf_tile_variants")
     return n
+
+
+def lnf_tile_config(h, dims, dtype: int, radius: int):
+    """(variant, zs) that lnf_filter would use for a volume of these dims."""
+    t = lnf_tile(-1, 0)
+    rc = lib().lnf_tile_config(h, _dims_t(*dims), dtype, radius, ctypes.byref(t))
+    if rc:
+        raise LnfError(rc, "lnf_tile_config")
+    return t.variant, t.zs
 
 
 def lnf_filter(h, vol, dims, dtype: int, radius: int, out, stream=None) -> int:

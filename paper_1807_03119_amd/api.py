@@ -47,6 +47,10 @@ class Filter:
             raise LnfError(rc, "lnf_filter")
         return out
 
+    def tile_config(self, dims, dtype: int, radius: int):
+        """(variant, zs) that a call on a volume of dims {nx, ny, nz} would use."""
+        return _lib.lnf_tile_config(self._h, dims, dtype, int(radius))
+
     def filter_otsu(self, vol, radius: int, out=None, stream=None):
         """The paper's automatic pipeline: Otsu threshold of `vol`, then the filter
         gated at it.  Returns (out, T)."""

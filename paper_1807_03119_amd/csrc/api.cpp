@@ -147,11 +147,11 @@ TileCfg ctx_tile(const lnf_ctx* h, int rule, int dtype, int radius, Geom g)
 }
 
 hipError_t launch_rule(int rule, uint32_t geom, const void* in, void* out, int dtype, int r,
-                       Geom g, uint32_t gate, TileCfg cfg, hipStream_t s)
+                       Geom g, uint32_t gate, TileCfg cfg, hipStream_t s, TileCfg* plan)
 {
-    if (geom) return launch_geometry(rule, geom, in, out, dtype, r, g, gate, cfg.zs, s);
-    if (rule == LNF_MEAN9) return launch_mean9(in, out, dtype, r, g, gate, cfg, s);
-    return launch_minvar9(in, out, dtype, r, g, gate, cfg, s);
+    if (geom) return launch_geometry(rule, geom, in, out, dtype, r, g, gate, cfg.zs, s, plan);
+    if (rule == LNF_MEAN9) return launch_mean9(in, out, dtype, r, g, gate, cfg, s, plan);
+    return launch_minvar9(in, out, dtype, r, g, gate, cfg, s, plan);
 }
 
 TuneKey tune_key(int rule, int dtype, int radius, Geom g)
@@ -281,6 +281,26 @@ int lnf_filter_tiled(lnf_handle h, const void* vol, const int64_t dims[3], int d
     if (launch_rule(h->rule, h->geom, vol, out, dtype, radius, g, h->gate, cfg, stream) !=
         hipSuccess)
         return LNF_EHIP;
+    return LNF_OK;
+}
+
+int lnf_tile_config(lnf_handle h, const int64_t dims[3], int dtype, int radius, lnf_tile* tile)
+{
+    if (!h || !dims || !tile) return LNF_EINVAL;
+    if (dtype != LNF_U8 && dtype != LNF_U16) return LNF_EINVAL;
+    if (radius < 1 || radius > LNF_RADIUS_MAX) return LNF_EINVAL;
+    for (int i = 0; i < 3; ++i)
+        if (dims[i] < 1 || dims[i] > INT_MAX) return LNF_EINVAL;
+    if (dims[0] * dims[1] > INT_MAX) return LNF_EINVAL;
+    const Geom g{(int)dims[0], (int)dims[1], (int)dims[2]};
+    TileCfg plan{-1, 0};
+    DeviceGuard dg(h->device);
+    if (!dg.ok()) return LNF_EHIP;
+    if (launch_rule(h->rule, h->geom, nullptr, nullptr, dtype, radius, g, h->gate,
+                    ctx_tile(h, h->rule, dtype, radius, g), nullptr, &plan) != hipSuccess)
+        return LNF_EHIP;
+    tile->variant = plan.variant;
+    tile->zs = plan.zs;
     return LNF_OK;
 }
 

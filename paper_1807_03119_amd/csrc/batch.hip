@@ -77,11 +77,11 @@ __device__ __forceinline__ const BatchJobDesc& job_of(const BatchTable* tab, con
 }
 
 template <int R, int TY, typename T, bool GATE, int TXW>
-__global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS))
-__attribute__((amdgpu_waves_per_eu(2))) void mean9_multi(
+__global__ __launch_bounds__((M9Geo<R, TY, TXW>::THREADS))
+__attribute__((amdgpu_waves_per_eu(R <= 3 ? 3 : 2))) void mean9_multi(
     const BatchTable* __restrict__ tab, int cls, uint32_t gate)
 {
-    __shared__ __align__(16) M9SmemAny<R, TY, TXW> sm;
+    __shared__ __align__(16) M9SmemAny<R, TY, TXW, T> sm;
     constexpr int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
     const BatchClass c = tab->c[cls];
     const int t = xcd_tile(blockIdx.x, c.total);
@@ -130,17 +130,17 @@ template <int R, typename T, bool GATE, int TY, int TXW>
 ClassKernel mean9_kernel()
 {
     return {reinterpret_cast<const void*>(mean9_multi<R, TY, T, GATE, TXW>),
-            M9Shape<R, TY, TXW>::THREADS};
+            M9Geo<R, TY, TXW>::THREADS};
 }
 
 template <int R, typename T, bool GATE>
 ClassKernel mean9_kernel_v(int variant)
 {
     switch (variant) {
-    case 2: return mean9_kernel<R, T, GATE, 32, 64>();
-    case 3: return mean9_kernel<R, T, GATE, 16, 32>();
-    case 4: return mean9_kernel<R, T, GATE, 32, 32>();
-    default: return mean9_kernel<R, T, GATE, 16, 64>();  // variants 0 and 1: 64 x 16
+    case 1: return mean9_kernel<R, T, GATE, 32, 64>();
+    case 2: return mean9_kernel<R, T, GATE, 16, 32>();
+    case 3: return mean9_kernel<R, T, GATE, 32, 32>();
+    default: return mean9_kernel<R, T, GATE, 16, 64>();  // variant 0: 64 x 16
     }
 }
 
@@ -311,7 +311,7 @@ int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>
         int variant = 0, tx = 32, ty = 8;
         if (h->rule == LNF_MEAN9) {
             const TileCfg cfg = ctx_tile(h, h->rule, dtype, r, geoms[order[k]]);
-            variant = cfg.variant >= 1 && cfg.variant < mean9_variants()
+            variant = cfg.variant >= 0 && cfg.variant < mean9_variants()
                           ? cfg.variant
                           : mean9_default_variant(dtype, r);
             mean9_tile_shape(variant, &tx, &ty);

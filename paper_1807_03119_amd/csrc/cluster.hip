@@ -30,13 +30,18 @@ __attribute__((amdgpu_waves_per_eu(PTShape<R, D, SHAPE, RULE>::WAVES))) void clu
 }
 
 template <int R, int D, int SHAPE, int RULE, typename T>
-hipError_t launch_geom(const void* in, void* out, Geom g, uint32_t gate, int zs, hipStream_t s)
+hipError_t launch_geom(const void* in, void* out, Geom g, uint32_t gate, int zs, hipStream_t s,
+                       TileCfg* plan)
 {
     using S = PTShape<R, D, SHAPE, RULE>;
     const auto kern = cluster_planes<R, D, SHAPE, RULE, T>;
     const int tiles_x = (g.nx + S::TX - 1) / S::TX, tiles_y = (g.ny + S::TY - 1) / S::TY;
     if (zs <= 0)
         zs = default_zs(tiles_x * tiles_y, g.nz, resident_groups((const void*)kern, S::THREADS));
+    if (plan) {
+        *plan = TileCfg{0, zs};
+        return hipSuccess;
+    }
     const int nzs = (g.nz + zs - 1) / zs;
     const int total = tiles_x * tiles_y * nzs;
     const double dn = (double)S::N;
@@ -48,40 +53,40 @@ hipError_t launch_geom(const void* in, void* out, Geom g, uint32_t gate, int zs,
 
 template <int R, int SHAPE, int RULE, typename T>
 hipError_t launch_offset(int offset, const void* in, void* out, Geom g, uint32_t gate, int zs,
-                         hipStream_t s)
+                         hipStream_t s, TileCfg* plan)
 {
     switch (offset) {
-    case LNF_GEOM_OFFSET_1: return launch_geom<R, 1, SHAPE, RULE, T>(in, out, g, gate, zs, s);
+    case LNF_GEOM_OFFSET_1: return launch_geom<R, 1, SHAPE, RULE, T>(in, out, g, gate, zs, s, plan);
     case LNF_GEOM_OFFSET_2R1:
-        return launch_geom<R, 2 * R + 1, SHAPE, RULE, T>(in, out, g, gate, zs, s);
-    default: return launch_geom<R, R, SHAPE, RULE, T>(in, out, g, gate, zs, s);
+        return launch_geom<R, 2 * R + 1, SHAPE, RULE, T>(in, out, g, gate, zs, s, plan);
+    default: return launch_geom<R, R, SHAPE, RULE, T>(in, out, g, gate, zs, s, plan);
     }
 }
 
 template <int R, typename T>
 hipError_t launch_r(int rule, uint32_t geom, const void* in, void* out, Geom g, uint32_t gate,
-                    int zs, hipStream_t s)
+                    int zs, hipStream_t s, TileCfg* plan)
 {
     const int offset = (int)(geom & (LNF_GEOM_OFFSET_1 | LNF_GEOM_OFFSET_2R1));
     const bool var = rule == LNF_MINVAR9;
     if (geom & LNF_GEOM_CROSS) {
         if (var)
-            return launch_offset<R, kClusterCross, kRuleMinVar9, T>(offset, in, out, g, gate, zs, s);
-        return launch_offset<R, kClusterCross, kRuleMean9, T>(offset, in, out, g, gate, zs, s);
+            return launch_offset<R, kClusterCross, kRuleMinVar9, T>(offset, in, out, g, gate, zs, s, plan);
+        return launch_offset<R, kClusterCross, kRuleMean9, T>(offset, in, out, g, gate, zs, s, plan);
     }
-    if (var) return launch_offset<R, kClusterBox, kRuleMinVar9, T>(offset, in, out, g, gate, zs, s);
-    return launch_offset<R, kClusterBox, kRuleMean9, T>(offset, in, out, g, gate, zs, s);
+    if (var) return launch_offset<R, kClusterBox, kRuleMinVar9, T>(offset, in, out, g, gate, zs, s, plan);
+    return launch_offset<R, kClusterBox, kRuleMean9, T>(offset, in, out, g, gate, zs, s, plan);
 }
 
 template <typename T>
 hipError_t dispatch(int rule, uint32_t geom, int r, const void* in, void* out, Geom g,
-                    uint32_t gate, int zs, hipStream_t s)
+                    uint32_t gate, int zs, hipStream_t s, TileCfg* plan)
 {
     switch (r) {
-    case 1: return launch_r<1, T>(rule, geom, in, out, g, gate, zs, s);
-    case 2: return launch_r<2, T>(rule, geom, in, out, g, gate, zs, s);
-    case 3: return launch_r<3, T>(rule, geom, in, out, g, gate, zs, s);
-    case 4: return launch_r<4, T>(rule, geom, in, out, g, gate, zs, s);
+    case 1: return launch_r<1, T>(rule, geom, in, out, g, gate, zs, s, plan);
+    case 2: return launch_r<2, T>(rule, geom, in, out, g, gate, zs, s, plan);
+    case 3: return launch_r<3, T>(rule, geom, in, out, g, gate, zs, s, plan);
+    case 4: return launch_r<4, T>(rule, geom, in, out, g, gate, zs, s, plan);
     default: return hipErrorInvalidValue;
     }
 }
@@ -89,10 +94,10 @@ hipError_t dispatch(int rule, uint32_t geom, int r, const void* in, void* out, G
 }  // namespace
 
 hipError_t launch_geometry(int rule, uint32_t geom, const void* in, void* out, int dtype, int r,
-                           Geom g, uint32_t gate, int zs, hipStream_t s)
+                           Geom g, uint32_t gate, int zs, hipStream_t s, TileCfg* plan)
 {
-    if (dtype == LNF_U8) return dispatch<uint8_t>(rule, geom, r, in, out, g, gate, zs, s);
-    return dispatch<uint16_t>(rule, geom, r, in, out, g, gate, zs, s);
+    if (dtype == LNF_U8) return dispatch<uint8_t>(rule, geom, r, in, out, g, gate, zs, s, plan);
+    return dispatch<uint16_t>(rule, geom, r, in, out, g, gate, zs, s, plan);
 }
 
 }  // namespace lnf

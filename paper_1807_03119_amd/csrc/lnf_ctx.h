@@ -54,8 +54,8 @@ int check_volume_args(const lnf_ctx* h, const void* vol, const int64_t dims[3], 
 int check_device_range(const void* p, size_t bytes, int device);
 TileCfg ctx_tile(const lnf_ctx* h, int rule, int dtype, int radius, Geom g);
 hipError_t launch_rule(int rule, uint32_t geom, const void* in, void* out, int dtype, int r,
-                       Geom g,
-                       uint32_t gate, TileCfg cfg, hipStream_t s);
+                       Geom g, uint32_t gate, TileCfg cfg, hipStream_t s,
+                       TileCfg* plan = nullptr);
 
 // Batch path (batch.hip).
 int validate_jobs(const lnf_ctx* h, const lnf_job* jobs, int n, std::vector<Geom>* geoms);

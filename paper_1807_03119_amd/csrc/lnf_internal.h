@@ -28,8 +28,10 @@ int mean9_variants();
 int mean9_default_variant(int dtype, int r);
 // Tile footprint of a variant: output tile width/height in x/y.
 void mean9_tile_shape(int variant, int* tx, int* ty);
+// With plan != nullptr the launchers only resolve the configuration they
+// would launch (tile variant and z-strip depth) into *plan and launch nothing.
 hipError_t launch_mean9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
-                        TileCfg cfg, hipStream_t s);
+                        TileCfg cfg, hipStream_t s, TileCfg* plan = nullptr);
 // Whether a volume can be staged as element pairs: even row length and a base
 // address aligned to a pair of elements.
 inline bool mean9_pairs_ok(const void* base, int nx, size_t elem)
@@ -39,7 +41,7 @@ inline bool mean9_pairs_ok(const void* base, int nx, size_t elem)
 
 // ---- geometry variants (plane_tile.h): LNF_GEOM_* bits, both rules ---------
 hipError_t launch_geometry(int rule, uint32_t geom, const void* in, void* out, int dtype, int r,
-                           Geom g, uint32_t gate, int zs, hipStream_t s);
+                           Geom g, uint32_t gate, int zs, hipStream_t s, TileCfg* plan = nullptr);
 // The paper's mean filter (eq. 4): rounded mean of the (2r+1)^3 cube, gated.
 hipError_t launch_box_mean(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
                            hipStream_t s);
@@ -52,7 +54,7 @@ hipError_t launch_window(int kind, const void* in, void* out, int dtype, int r, 
 int minvar9_variants();
 void minvar9_tile_shape(int variant, int r, int* tx, int* ty);  // output tile of (variant, r)
 hipError_t launch_minvar9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
-                          TileCfg cfg, hipStream_t s);
+                          TileCfg cfg, hipStream_t s, TileCfg* plan = nullptr);
 
 // Default z-strip depth: nz split into enough strips that tiles_xy * strips
 // reaches target_groups (strips no shallower than 16 slices).

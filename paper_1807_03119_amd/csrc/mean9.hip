@@ -20,181 +20,22 @@
 namespace lnf {
 namespace {
 
-constexpr int kThreads = 256;
-
-// Output tile 64 (x) x 16 (y) per workgroup, streaming `zs` slices in z.
-// Per input slice:
-//   1. the raw (64+4r) x (16+4r) slice tile (clamped at the volume faces) is
-//      written from registers into LDS, and the next slice's loads are issued;
-//   2. x-pass: 8-wide row segments, prefix sums over the 8+4r raw values give
-//      px = box_x E and qx = c_x E for the 16+4r rows;
-//   3. y-pass: each thread owns one column x and four consecutive rows and
-//      forms P = box_y px and Q = c_y qx from prefix sums over the column;
-//   4. z-window: a ring of the last 4r+2 (P, Q) slices in registers keeps the
-//      running sums B = box_z P (lagging 2r slices) and W = sum of Q over
-//      [-2r, 2r]; the output slice z = zi - 2r is S = B + W + Q(z).
-template <int R, typename T, bool GATE>
-__global__ __launch_bounds__(kThreads) void mean9_ring_64x16(const T* __restrict__ in,
-                                                             T* __restrict__ out, Geom g, int zs,
-                                                             int tiles_x, int tiles_y, int total,
-                                                             uint32_t gate, double inv9n)
+// Waves per SIMD the tile kernels are compiled for: three up to r = 3 (the
+// tile body fits 168 VGPRs there), two at r = 4.
+template <int R>
+constexpr int m9_waves()
 {
-    constexpr int TX = 64, TY = 16, H = 2 * R;
-    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
-    constexpr int NRAW = LX * LY;
-    constexpr int NLOAD = (NRAW + kThreads - 1) / kThreads;
-    constexpr int NFULL = NRAW / kThreads;
-    constexpr int D = 4 * R + 2;  // ring period (slices kept per output column)
-    constexpr int SEG = 8, NSEG = TX / SEG, SW = SEG + 4 * R;
-    constexpr int YO = 4;  // outputs per thread along y
-    constexpr int NPV = YO + 2 * R, NQV = YO + 4 * R;
-    static_assert(LY * NSEG <= kThreads, "x-pass needs one thread per row segment");
-    static_assert(TX * (TY / YO) == kThreads, "y-pass needs one thread per column quad");
-
-    __shared__ __align__(16) uint32_t s_raw[LY * LX];
-    __shared__ __align__(16) uint32_t s_px[LY * TX];
-    __shared__ __align__(16) uint32_t s_qx[LY * TX];
-
-    const int tid = threadIdx.x;
-    const int tile = xcd_tile(blockIdx.x, total);
-    const int bx = tile % tiles_x;
-    const int rest = tile / tiles_x;
-    const int by = rest % tiles_y;
-    const int bz = rest / tiles_y;
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * zs;
-    const int z1 = min(z0 + zs, g.nz);
-    const size_t plane = (size_t)g.nx * g.ny;
-
-    // In-slice offsets of the raw elements this thread stages (clamped).
-    int off[NLOAD];
-#pragma unroll
-    for (int i = 0; i < NLOAD; ++i) {
-        const int e = min(tid + i * kThreads, NRAW - 1);
-        const int row = e / LX, col = e - row * LX;
-        const int gy = clampi(y0 - H + row, 0, g.ny - 1);
-        const int gx = clampi(x0 - H + col, 0, g.nx - 1);
-        off[i] = gy * g.nx + gx;
-    }
-    const bool last_ok = tid + (NLOAD - 1) * kThreads < NRAW;
-
-    uint32_t v[NLOAD];
-    auto load = [&](int zi) {
-        const T* base = in + (size_t)clampi(zi, 0, g.nz - 1) * plane;
-#pragma unroll
-        for (int i = 0; i < NLOAD; ++i) v[i] = base[off[i]];
-    };
-
-    const int xrow = tid / NSEG, xseg = tid % NSEG;
-    const bool xactive = xrow < LY;
-    const int xq = tid % TX, yg = tid / TX;
-
-    uint32_t pr[D][YO], qr[D][YO], bacc[YO], wacc[YO];
-#pragma unroll
-    for (int m = 0; m < YO; ++m) {
-        bacc[m] = wacc[m] = 0;
-#pragma unroll
-        for (int u = 0; u < D; ++u) pr[u][m] = qr[u][m] = 0;
-    }
-
-    const int ns = (z1 - z0) + 2 * H;  // input slices z0-2r .. z1-1+2r
-    load(z0 - H);
-    for (int kb = 0; kb < ns; kb += D) {
-#pragma unroll
-        for (int u = 0; u < D; ++u) {
-            const int k = kb + u;
-            if (k >= ns) break;
-            // 1. stage slice k, prefetch slice k+1
-#pragma unroll
-            for (int i = 0; i < NLOAD; ++i)
-                if (i < NFULL || last_ok) s_raw[tid + i * kThreads] = v[i];
-            if (k + 1 < ns) load(z0 - H + k + 1);
-            __syncthreads();
-
-            // 2. x-pass
-            if (xactive) {
-                uint32_t w[SW], c[SW];
-                const uint32_t* rp = s_raw + xrow * LX + xseg * SEG;
-#pragma unroll
-                for (int i = 0; i < SW; i += 4) {
-                    const uint4 t4 = *reinterpret_cast<const uint4*>(rp + i);
-                    w[i] = t4.x;
-                    w[i + 1] = t4.y;
-                    w[i + 2] = t4.z;
-                    w[i + 3] = t4.w;
-                }
-                c[0] = w[0];
-#pragma unroll
-                for (int i = 1; i < SW; ++i) c[i] = c[i - 1] + w[i];
-                uint32_t pp[SEG], qq[SEG];
-#pragma unroll
-                for (int m = 0; m < SEG; ++m) {
-                    qq[m] = c[m + 4 * R] - (m ? c[m - 1] : 0u) + w[m + 2 * R];
-                    pp[m] = c[m + 3 * R] - c[m + R - 1];
-                }
-                uint32_t* pd = s_px + xrow * TX + xseg * SEG;
-                uint32_t* qd = s_qx + xrow * TX + xseg * SEG;
-#pragma unroll
-                for (int m = 0; m < SEG; m += 4) {
-                    *reinterpret_cast<uint4*>(pd + m) = make_uint4(pp[m], pp[m + 1], pp[m + 2], pp[m + 3]);
-                    *reinterpret_cast<uint4*>(qd + m) = make_uint4(qq[m], qq[m + 1], qq[m + 2], qq[m + 3]);
-                }
-            }
-            __syncthreads();
-
-            // 3. y-pass for rows yg*4 .. yg*4+3 of column xq
-            uint32_t cp[NPV], cq[NQV], qc[YO];
-            cp[0] = s_px[(yg * YO + R) * TX + xq];
-#pragma unroll
-            for (int i = 1; i < NPV; ++i) cp[i] = cp[i - 1] + s_px[(yg * YO + R + i) * TX + xq];
-            {
-                uint32_t qv[NQV];
-#pragma unroll
-                for (int i = 0; i < NQV; ++i) qv[i] = s_qx[(yg * YO + i) * TX + xq];
-                cq[0] = qv[0];
-#pragma unroll
-                for (int i = 1; i < NQV; ++i) cq[i] = cq[i - 1] + qv[i];
-#pragma unroll
-                for (int m = 0; m < YO; ++m) qc[m] = qv[m + 2 * R];
-            }
-
-            // 4. z-window over the register ring
-#pragma unroll
-            for (int m = 0; m < YO; ++m) {
-                const uint32_t P = cp[m + 2 * R] - (m ? cp[m - 1] : 0u);
-                const uint32_t Q = cq[m + 4 * R] - (m ? cq[m - 1] : 0u) + qc[m];
-                bacc[m] += pr[(u + D - R) % D][m] - pr[(u + R + 1) % D][m];
-                wacc[m] += Q - qr[(u + 1) % D][m];
-                pr[u][m] = P;
-                qr[u][m] = Q;
-            }
-            if (k >= 2 * H) {
-                const int z = z0 + k - 2 * H;
-                T* op = out + (size_t)z * plane;
-                const int x = x0 + xq;
-#pragma unroll
-                for (int m = 0; m < YO; ++m) {
-                    const uint32_t S = bacc[m] + wacc[m] + qr[(u + D - 2 * R) % D][m];
-                    uint32_t o = round_div_odd(S, inv9n);
-                    if (GATE && o < gate) o = 0;
-                    const int y = y0 + yg * YO + m;
-                    if (x < g.nx && y < g.ny) op[(size_t)y * g.nx + x] = (T)o;
-                }
-            }
-        }
-    }
+    return R <= 3 ? 3 : 2;
 }
 
 // Single-volume wrapper around the streaming tile body of mean9_tile.h.
-// At least 2 waves per SIMD: at r = 4 the tile would take 274-285 VGPRs (one
-// wave per SIMD); capped at 256 it spills a little and still runs faster
-// (512^3, r = 4: uint16 406 -> 425, uint8 418 -> 466 Gvox/s); r <= 3 fits anyway.
 template <int R, int TY, typename T, bool GATE, int TXW>
-__global__ __launch_bounds__((M9Shape<R, TY, TXW>::THREADS))
-__attribute__((amdgpu_waves_per_eu(2))) void mean9_stream(
+__global__ __launch_bounds__((M9Geo<R, TY, TXW>::THREADS))
+__attribute__((amdgpu_waves_per_eu(m9_waves<R>()))) void mean9_stream(
     const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
     int total, uint32_t gate, double inv9n, int pairs)
 {
-    __shared__ __align__(16) M9SmemAny<R, TY, TXW> sm;
+    __shared__ __align__(16) M9SmemAny<R, TY, TXW, T> sm;
     const int tile = xcd_tile(blockIdx.x, total);
     const int bx = tile % tiles_x;
     const int rest = tile / tiles_x;
@@ -208,11 +49,12 @@ __attribute__((amdgpu_waves_per_eu(2))) void mean9_stream(
 // The paper's mean filter (eq. 4): the box term of the same streaming tile,
 // 64 x 16 tiles.
 template <int R, typename T, bool GATE>
-__global__ __launch_bounds__((M9Shape<R, 16, 64>::THREADS)) void box_mean_stream(
+__global__ __launch_bounds__((M9Geo<R, 16, 64>::THREADS))
+__attribute__((amdgpu_waves_per_eu(m9_waves<R>()))) void box_mean_stream(
     const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
     int total, uint32_t gate, double invn, int pairs)
 {
-    __shared__ __align__(16) M9SmemAny<R, 16, 64, true> sm;
+    __shared__ __align__(16) M9SmemAny<R, 16, 64, T, true> sm;
     const int tile = xcd_tile(blockIdx.x, total);
     const int bx = tile % tiles_x;
     const int rest = tile / tiles_x;
@@ -226,7 +68,7 @@ __global__ __launch_bounds__((M9Shape<R, 16, 64>::THREADS)) void box_mean_stream
 template <int R, typename T, bool GATE>
 hipError_t launch_box(const T* in, T* out, Geom g, uint32_t gate, hipStream_t s)
 {
-    constexpr int threads = M9Shape<R, 16, 64>::THREADS;
+    constexpr int threads = M9Geo<R, 16, 64>::THREADS;
     const auto kern = box_mean_stream<R, T, GATE>;
     const int tiles_x = (g.nx + 63) / 64, tiles_y = (g.ny + 15) / 16;
     const int zs = default_zs(tiles_x * tiles_y, g.nz, resident_groups((const void*)kern, threads));
@@ -255,27 +97,29 @@ hipError_t dispatch_box(int r, const void* in, void* out, Geom g, uint32_t gate,
 struct Variant {
     int tx, ty, threads;
 };
-// 0: first design (two barriers per slice, register staging)
-// 1-4: LDS-DMA staging ring, one barrier per slice; 64 or 32 wide, 16 or 32 high
-constexpr Variant kVariants[] = {{64, 16, 256}, {64, 16, 256}, {64, 32, 512}, {32, 16, 128},
-                                 {32, 32, 256}};
+// output tiles of the compiled shapes: 64 or 32 wide, 16 or 32 high
+constexpr Variant kVariants[] = {{64, 16, 256}, {64, 32, 512}, {32, 16, 128}, {32, 32, 256}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // Default variant per voxel type and radius (index r-1): the fastest at the
 // default z-strip depth on 512^3 volumes.
-constexpr int kDefaultU16[LNF_RADIUS_MAX] = {2, 1, 1, 4};
-constexpr int kDefaultU8[LNF_RADIUS_MAX] = {2, 4, 3, 3};
+constexpr int kDefaultU16[LNF_RADIUS_MAX] = {0, 0, 0, 3};
+constexpr int kDefaultU8[LNF_RADIUS_MAX] = {0, 0, 0, 3};
 
 template <int R, typename T, bool GATE, int TY, int TXW>
-hipError_t launch_stream(const T* in, T* out, Geom g, uint32_t gate, int zs, hipStream_t s)
+hipError_t launch_stream(const T* in, T* out, Geom g, uint32_t gate, int zs, hipStream_t s,
+                         TileCfg* plan)
 {
-    static_assert(M9Shape<R, TY, TXW, true>::THREADS == M9Shape<R, TY, TXW>::THREADS, "");
-    constexpr int threads = M9Shape<R, TY, TXW>::THREADS;
+    constexpr int threads = M9Geo<R, TY, TXW>::THREADS;
     const auto kern = mean9_stream<R, TY, T, GATE, TXW>;
     const int tiles_x = (g.nx + TXW - 1) / TXW, tiles_y = (g.ny + TY - 1) / TY;
     // default z-strip depth: one full round of resident workgroups
     if (zs <= 0)
         zs = default_zs(tiles_x * tiles_y, g.nz, resident_groups((const void*)kern, threads));
+    if (plan) {
+        plan->zs = zs;
+        return hipSuccess;
+    }
     const int nzs = (g.nz + zs - 1) / zs;
     const int total = tiles_x * tiles_y * nzs;
     const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
@@ -287,48 +131,40 @@ hipError_t launch_stream(const T* in, T* out, Geom g, uint32_t gate, int zs, hip
 
 template <int R, typename T, bool GATE>
 hipError_t launch_variant(int variant, const void* in, void* out, Geom g, uint32_t gate, int zs,
-                          hipStream_t s)
+                          hipStream_t s, TileCfg* plan)
 {
     const T* pin = static_cast<const T*>(in);
     T* pout = static_cast<T*>(out);
     switch (variant) {
-    case 0: {
-        const int tiles_x = (g.nx + 63) / 64, tiles_y = (g.ny + 15) / 16;
-        if (zs <= 0) zs = default_zs(tiles_x * tiles_y, g.nz, 1024);
-        const int total = tiles_x * tiles_y * ((g.nz + zs - 1) / zs);
-        const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
-        hipLaunchKernelGGL((mean9_ring_64x16<R, T, GATE>), dim3(total), dim3(kThreads), 0, s, pin,
-                           pout, g, zs, tiles_x, tiles_y, total, gate, 1.0 / (9.0 * n));
-        return hipGetLastError();
-    }
-    case 1: return launch_stream<R, T, GATE, 16, 64>(pin, pout, g, gate, zs, s);
-    case 2: return launch_stream<R, T, GATE, 32, 64>(pin, pout, g, gate, zs, s);
-    case 3: return launch_stream<R, T, GATE, 16, 32>(pin, pout, g, gate, zs, s);
-    default: return launch_stream<R, T, GATE, 32, 32>(pin, pout, g, gate, zs, s);
+    case 0: return launch_stream<R, T, GATE, 16, 64>(pin, pout, g, gate, zs, s, plan);
+    case 1: return launch_stream<R, T, GATE, 32, 64>(pin, pout, g, gate, zs, s, plan);
+    case 2: return launch_stream<R, T, GATE, 16, 32>(pin, pout, g, gate, zs, s, plan);
+    default: return launch_stream<R, T, GATE, 32, 32>(pin, pout, g, gate, zs, s, plan);
     }
 }
 
 template <int R, typename T>
 hipError_t launch_r(int variant, const void* in, void* out, Geom g, uint32_t gate, int zs,
-                    hipStream_t s)
+                    hipStream_t s, TileCfg* plan)
 {
-    if (gate) return launch_variant<R, T, true>(variant, in, out, g, gate, zs, s);
-    return launch_variant<R, T, false>(variant, in, out, g, gate, zs, s);
+    if (gate) return launch_variant<R, T, true>(variant, in, out, g, gate, zs, s, plan);
+    return launch_variant<R, T, false>(variant, in, out, g, gate, zs, s, plan);
 }
 
 template <typename T>
 hipError_t dispatch_r(const void* in, void* out, int r, Geom g, uint32_t gate, TileCfg cfg,
-                      hipStream_t s)
+                      hipStream_t s, TileCfg* plan)
 {
     if (r < 1 || r > LNF_RADIUS_MAX) return hipErrorInvalidValue;
     const int v = (cfg.variant >= 0 && cfg.variant < kNumVariants)
                       ? cfg.variant
                       : mean9_default_variant(sizeof(T) == 1 ? LNF_U8 : LNF_U16, r);
+    if (plan) plan->variant = v;
     switch (r) {
-    case 1: return launch_r<1, T>(v, in, out, g, gate, cfg.zs, s);
-    case 2: return launch_r<2, T>(v, in, out, g, gate, cfg.zs, s);
-    case 3: return launch_r<3, T>(v, in, out, g, gate, cfg.zs, s);
-    default: return launch_r<4, T>(v, in, out, g, gate, cfg.zs, s);
+    case 1: return launch_r<1, T>(v, in, out, g, gate, cfg.zs, s, plan);
+    case 2: return launch_r<2, T>(v, in, out, g, gate, cfg.zs, s, plan);
+    case 3: return launch_r<3, T>(v, in, out, g, gate, cfg.zs, s, plan);
+    default: return launch_r<4, T>(v, in, out, g, gate, cfg.zs, s, plan);
     }
 }
 
@@ -344,7 +180,7 @@ int mean9_default_variant(int dtype, int r)
 
 void mean9_tile_shape(int variant, int* tx, int* ty)
 {
-    const Variant v = kVariants[(variant >= 0 && variant < kNumVariants) ? variant : 1];
+    const Variant v = kVariants[(variant >= 0 && variant < kNumVariants) ? variant : 0];
     *tx = v.tx;
     *ty = v.ty;
 }
@@ -357,10 +193,10 @@ hipError_t launch_box_mean(const void* in, void* out, int dtype, int r, Geom g, 
 }
 
 hipError_t launch_mean9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
-                        TileCfg cfg, hipStream_t s)
+                        TileCfg cfg, hipStream_t s, TileCfg* plan)
 {
-    if (dtype == LNF_U8) return dispatch_r<uint8_t>(in, out, r, g, gate, cfg, s);
-    return dispatch_r<uint16_t>(in, out, r, g, gate, cfg, s);
+    if (dtype == LNF_U8) return dispatch_r<uint8_t>(in, out, r, g, gate, cfg, s, plan);
+    return dispatch_r<uint16_t>(in, out, r, g, gate, cfg, s, plan);
 }
 
 }  // namespace lnf

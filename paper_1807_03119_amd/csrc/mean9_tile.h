@@ -1,34 +1,53 @@
 // Streaming MEAN9 tile body: one workgroup filters a TX x TY column of output
-// voxels over the z-range [z0, z1).  Shared by the single-volume kernel and the
-// persistent batch kernel.
+// voxels over the z-range [z0, z1).  Shared by the single-volume kernel, the
+// mean filter and the batch kernel.
 //
 // Arithmetic (paper, Section "Our Method", eqs. 2-3): the sum S over the nine
 // clusters is box_x box_y box_z E + c_x c_y c_z E, with box = ones on [-r, r]
 // and c = ones on [-2r, 2r] plus one more at the centre (the two diagonal
-// clusters of an axis overlap there).  Everything is exact uint32.
+// clusters of an axis overlap there).  Per axis c = box shifted by -r plus box
+// shifted by +r.  Everything is exact uint32.
 //
-// Pipeline per input slice k, in issue order within one iteration (one
-// barrier per iteration):
-//   - stores of the output slice finished in the previous iteration;
-//   - LDS reads of everything the iteration consumes: this thread's raw row
-//     segment of slice k and its px / qx column of slice k-1;
-//   - y-pass of slice k-1: each thread owns one column and four rows, forms
-//     P = box_y px and Q = c_y qx from prefix sums, and pushes them into a
-//     register ring of the last 4r+2 slices; the ring keeps the running sums
-//     B = sum of P over [z-r, z+r] and W = sum of Q over [z-2r, z+2r] for the
-//     output slice z, two r behind the newest slice, and S = B + W + Q(z);
-//     out = round(S / 9n) (fp64, exact), gate;
-//   - LDS DMA: the raw (TX+4r) x (TY+4r) tile of slice k+PF is loaded straight
-//     from HBM into LDS (one element per lane, zero-extended to 32 bits), its
-//     coordinates clamped into the volume per lane; PF+1 raw buffers form a
-//     ring, so each slice has PF iterations to arrive;
-//   - x-pass of slice k: each thread takes an 8-wide row segment, forms prefix
-//     sums over its 8+4r raw values and writes px = box_x E and qx = c_x E.
-// px and qx are double-buffered, so the x-pass of slice k overlaps the y-pass
-// of slice k-1.  Every iteration issues exactly NLOAD loads and YO stores (no
-// branch around any of them: masked-off stores go to an offset the buffer's
-// range check drops), so the wait for slice k+1 at the end of iteration k is
-// a partial one that leaves the younger PF-1 iterations' operations in flight.
+// Per input slice s the x- and y-passes give the plane sums
+//   P(s) = box_y box_x E(s),   Q(s) = c_y c_x E(s)
+// at each output column.  Along z, c_z = box_z shifted by -r plus by +r, so
+//   S(z) = sum_{t=z-r..z+r} P(t) + sum_{t=z-r..z+r} Q(t-r) + sum_{t=z-r..z+r} Q(t+r)
+//        = sum_{t=z..z+2r} G(t),   G(t) = P(t-r) + Q(t) + Q(t-2r),
+// a running box of 2r+1 slices of one quantity.  A value of P is kept r
+// slices, of Q 2r slices and of G 2r+1 slices: 5r+1 registers per output
+// column, in a register ring of D = 2r+2 slots indexed statically by the
+// unrolled loop (the allocator keeps only the live values).
+//
+// Pipeline per iteration k (one barrier per iteration):
+//   - LDS reads of this thread's raw row segment of slice k and of its x-pass
+//     column of slice k-1;
+//   - y-pass of slice k-1 (each thread owns one column and YO = 4 rows; prefix
+//     sums), G, the running sum, out = round(S / 9n) (fp64, exact), gate and
+//     the stores of output slice k-1-4r;
+//   - LDS DMA of the raw (TX+4r) x (TY+4r) tile of slice k+PF straight from
+//     HBM into LDS, coordinates clamped into the volume per lane; NRB = PF+1
+//     raw buffers form a ring, so each slice has PF iterations to arrive;
+//   - x-pass of slice k: each thread takes an 8-wide row segment and forms
+//     px = box_x E and qx = c_x E from prefix sums over its 8+4r raw values.
+// The x-pass results are double-buffered, so the x-pass of slice k overlaps
+// the y-pass of slice k-1.  Every iteration issues exactly NLOAD loads and YO
+// stores (masked-off stores go to an offset the buffer's range check drops),
+// so the wait for slice k+1 at the end of iteration k is a partial one that
+// leaves the younger PF-1 iterations' operations in flight.
+//
+// Modes:
+//   kM9Packed  px <= qx, and when qx < 2^16 both fit one LDS word px | qx<<16.
+//              The x-pass stores half as much and a y-pass thread loads 4+4r
+//              words instead of (4+2r) + (4+4r): its px rows lie inside its qx
+//              rows.  Whether qx < 2^16 depends on the data (always for values
+//              up to 65535 / (4r+2): uint8, or 12-bit data up to r = 3), so
+//              the x-pass ORs together every qx it forms; at the end of each
+//              block of D slices the workgroup checks the OR, and a tile that
+//              saw qx >= 2^16 stops: the caller filters it again in kM9Exact,
+//              which rewrites every output of the tile.  Exact for every input.
+//   kM9Exact   px and qx in separate uint32 LDS words.
+//   kM9Box     the box term alone (the paper's mean filter, eq. 4): px only,
+//              S(z) = sum_{t=z-r..z+r} P(t).
 #pragma once
 
 #include "device_common.h"
@@ -36,19 +55,17 @@
 
 namespace lnf {
 
-#ifndef LNF_M9_PREFETCH
-#define LNF_M9_PREFETCH 2
-#endif
+constexpr int kM9Exact = 0, kM9Packed = 1, kM9Box = 2;
 
-// PK: the raw tile is staged as element pairs, one 32-bit LDS word per pair
-// (uint16: both halves; uint8: the low two bytes), loaded by one LDS DMA per
-// lane.  That halves the DMA instructions and the LDS bytes of the staging and
-// of the x-pass reads.  It needs an even nx (pairs never straddle a row end), a
-// volume base aligned to a pair, and a tile whose halo stays inside the volume
-// in x (a pair cannot be clamped element by element); tiles at an x face are
-// staged element-wise.
+// Tile geometry.  PK: the raw tile is staged as element pairs, one 32-bit LDS
+// word per pair (uint16: both halves; uint8: the low two bytes), loaded by one
+// LDS DMA per lane.  That halves the DMA instructions and the LDS bytes of the
+// staging and of the x-pass reads.  It needs an even nx (pairs never straddle
+// a row end), a volume base aligned to a pair, and a tile whose halo stays
+// inside the volume in x (a pair cannot be clamped element by element); tiles
+// at an x face are staged element-wise.
 template <int R, int TY, int TXW = 64, bool PK = false>
-struct M9Shape {
+struct M9Geo {
     static constexpr int TX = TXW;
     static constexpr int YO = 4;                    // output rows per thread
     static constexpr int THREADS = TX * TY / YO;    // one thread per column x YO rows
@@ -64,43 +81,81 @@ struct M9Shape {
     static constexpr int LY = TY + 2 * H;
     static constexpr int NRAW = LX * LY;            // staged words per slice
     static constexpr int NLOAD = (NRAW + THREADS - 1) / THREADS;
-    static constexpr int PXP = TX + 4;              // padded px/qx row pitch (words)
-    static constexpr int D = 4 * R + 2;             // ring period (even)
+    static constexpr int RAWW = NLOAD * THREADS;    // words of one raw buffer
+    static constexpr int PXP = TX + 4;              // padded x-pass row pitch (words)
+    static constexpr int XPW = (LY + 1) * PXP;      // words of one x-pass buffer
+    static constexpr int D = 2 * R + 2;             // ring period and unroll (even)
     static constexpr int SEG = 8, NSEG = TX / SEG, SW = SEG + 4 * R;
     static constexpr int SWW = SW / EPW;            // words an x-pass segment reads
     static constexpr int XR = (LY + 7) / 8 * 8;     // x-pass row slots (multiple of 8)
     static constexpr int NPV = YO + 2 * R, NQV = YO + 4 * R;
-    static constexpr int PF = LNF_M9_PREFETCH;       // slices staged ahead of the x-pass
-    static constexpr int NRB = PF + 1;               // raw slice buffers (a ring)
-    // vector-memory operations issued after a slice's loads, up to the wait
-    // that needs that slice: PF-1 iterations of (NLOAD loads + YO stores)
-    static constexpr int VMWAIT = (PF - 1) * (NLOAD + YO);
-    static_assert(PF >= 1 && VMWAIT <= 63, "prefetch depth out of range");
     static_assert(XR * NSEG <= THREADS, "x-pass: one thread per row segment");
     static_assert(D % 2 == 0, "buffer parity must be static in the unrolled ring");
     static_assert(LX % 4 == 0 && (SEG / EPW) % 4 == 0, "x-pass reads 16-byte aligned rows");
     static_assert(SWW % 2 == 0 && LXE % 2 == 0, "x-pass reads whole 8-byte pieces");
 };
 
-// BOX: the box term alone (the paper's mean filter, eq. 4): no qx, no Q ring.
-template <int R, int TY, int TXW = 64, bool PK = false, bool BOX = false>
-struct M9Smem {
-    using S = M9Shape<R, TY, TXW, PK>;
-    uint32_t raw[S::NRB][S::NLOAD * S::THREADS];
-    uint32_t px[2][S::LY * S::PXP];
-    uint32_t qx[BOX ? 1 : 2][BOX ? 1 : S::LY * S::PXP];
+// LDS one workgroup may use: three 256-thread workgroups per CU (160 KiB).
+constexpr int kM9LdsBudget = 53 * 1024;
+
+template <int R, int TY, int TXW, bool PK, int MODE>
+struct M9Shape : M9Geo<R, TY, TXW, PK> {
+    using G = M9Geo<R, TY, TXW, PK>;
+    static constexpr int XBUFS = MODE == kM9Exact ? 4 : 2;  // px (and qx), double-buffered
+    static constexpr int bytes_for(int nrb) { return 4 * (XBUFS * G::XPW + nrb * G::RAWW) + 16; }
+    // Raw buffers: the largest count up to 5 that divides the unroll (so a
+    // slice's buffer index is static), keeps the partial wait within the 6-bit
+    // counter and fits the budget (the least, 2, if none does).
+    static constexpr int pick_nrb()
+    {
+        for (int n = 5; n > 2; --n)
+            if (G::D % n == 0 && (n - 2) * (G::NLOAD + G::YO) <= 63 &&
+                bytes_for(n) <= kM9LdsBudget)
+                return n;
+        return 2;
+    }
+    static constexpr int NRB = pick_nrb();
+    static constexpr int PF = NRB - 1;  // slices staged ahead of the x-pass
+    // vector-memory operations issued after a slice's loads, up to the wait
+    // that needs that slice: PF-1 iterations of (NLOAD loads + YO stores)
+    static constexpr int VMWAIT = (PF - 1) * (G::NLOAD + G::YO);
+    static_assert(G::D % NRB == 0 && VMWAIT <= 63, "raw ring");
 };
 
-// inv_div: 1/(9n), or 1/n with BOX.
-template <int R, int TY, typename T, bool GATE, int TXW, bool PK, bool BOX = false>
-__device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK, BOX>& sm,
+template <int R, int TY, int TXW, bool PK, int MODE>
+struct M9Smem {
+    using S = M9Shape<R, TY, TXW, PK, MODE>;
+    uint32_t raw[S::NRB][S::RAWW];
+    // x-pass results; the extra row LY takes the surplus x-pass lanes' stores,
+    // so no two lanes of a store hit the same address
+    uint32_t px[2][S::XPW];
+    uint32_t qx[MODE == kM9Exact ? 2 : 1][MODE == kM9Exact ? S::XPW : 1];
+    uint32_t flag;  // kM9Packed: some x-pass of the tile formed qx >= 2^16
+};
+
+// Whether packed mode can see qx >= 2^16 for this element type and radius.
+template <typename T, int R>
+constexpr bool m9_packed_may_overflow()
+{
+    return (uint64_t)(4 * R + 2) * ((1u << (8 * sizeof(T))) - 1u) >= 65536u;
+}
+
+// inv_div: 1/(9n), or 1/n with kM9Box.  Returns false when a kM9Packed tile
+// stopped because some qx did not fit 16 bits; its outputs are then
+// incomplete and the tile must be filtered again in kM9Exact.
+template <int R, int TY, typename T, bool GATE, int TXW, bool PK, int MODE>
+__device__ __forceinline__ bool mean9_tile_body(M9Smem<R, TY, TXW, PK, MODE>& sm,
                                                 const T* __restrict__ in, T* __restrict__ out,
                                                 Geom g, int x0, int y0, int z0, int z1,
-                                                uint32_t gate, double inv9n)
+                                                uint32_t gate, double inv_div)
 {
-    using S = M9Shape<R, TY, TXW, PK>;
+    using S = M9Shape<R, TY, TXW, PK, MODE>;
+    constexpr bool kBox = MODE == kM9Box, kPQ = MODE == kM9Packed;
+    constexpr bool kCheck = kPQ && m9_packed_may_overflow<T, R>();
     constexpr int H = S::H, LX = S::LX, D = S::D, TX = S::TX, PXP = S::PXP, YO = S::YO;
-    constexpr int EPW = S::EPW;
+    constexpr int EPW = S::EPW, NRB = S::NRB, PF = S::PF;
+    // output slice of iteration k: z0 + k - 1 - LAG
+    constexpr int LAG = kBox ? 3 * R : 4 * R;
     const int tid = threadIdx.x;
     // wave index as a scalar, so the LDS DMA destinations are scalar arithmetic
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -135,9 +190,10 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK, BOX>& sm,
     const int xq = tid % TX;
     // x-pass mapping: consecutive lanes take consecutive rows of one segment
     // (bank-conflict free with the padded pitch).  Row slots are padded to a
-    // multiple of 8; surplus lanes and threads redo the last row or segment and
-    // write the same values, so the x-pass needs no divergent branch.
+    // multiple of 8; surplus lanes redo the last row (no divergent branch) and
+    // store to the spare row LY.
     const int xrow = min(tid % S::XR, S::LY - 1);
+    const int xroww = (tid % S::XR < S::LY) ? xrow : S::LY;
     const int xseg = min(tid / S::XR, S::NSEG - 1);
     auto half = [](uint32_t w, int h) -> uint32_t {
         return h ? (w >> (8 * sizeof(T))) : (w & ((1u << (8 * sizeof(T))) - 1u));
@@ -162,7 +218,9 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK, BOX>& sm,
             }
         }
     };
-    // x-pass, part 2: prefix sums over the segment, px and qx written to LDS;
+    // OR of every qx this thread formed (kM9Packed: must stay below 2^16)
+    uint32_t qor = 0;
+    // x-pass, part 2: prefix sums over the segment, results written to LDS;
     // el(i) is raw element i of the segment
     auto xsums = [&](int buf, auto el) {
         uint32_t pp[S::SEG], qq[S::SEG], c[S::SW];
@@ -171,15 +229,22 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK, BOX>& sm,
         for (int i = 1; i < S::SW; ++i) c[i] = c[i - 1] + el(i);
 #pragma unroll
         for (int m = 0; m < S::SEG; ++m) {
-            if constexpr (!BOX) qq[m] = c[m + 4 * R] - (m ? c[m - 1] : 0u) + el(m + 2 * R);
+            if constexpr (!kBox) qq[m] = c[m + 4 * R] - (m ? c[m - 1] : 0u) + el(m + 2 * R);
             pp[m] = c[m + 3 * R] - c[m + R - 1];
         }
-        uint32_t* pd = sm.px[buf] + xrow * PXP + xseg * S::SEG;
+        if constexpr (kPQ) {
+#pragma unroll
+            for (int m = 0; m < S::SEG; ++m) {
+                if constexpr (kCheck) qor |= qq[m];
+                pp[m] |= qq[m] << 16;
+            }
+        }
+        uint32_t* pd = sm.px[buf] + xroww * PXP + xseg * S::SEG;
 #pragma unroll
         for (int m = 0; m < S::SEG; m += 4) {
             *reinterpret_cast<uint4*>(pd + m) = make_uint4(pp[m], pp[m + 1], pp[m + 2], pp[m + 3]);
-            if constexpr (!BOX) {
-                uint32_t* qd = sm.qx[buf] + xrow * PXP + xseg * S::SEG;
+            if constexpr (MODE == kM9Exact) {
+                uint32_t* qd = sm.qx[buf] + xroww * PXP + xseg * S::SEG;
                 *reinterpret_cast<uint4*>(qd + m) =
                     make_uint4(qq[m], qq[m + 1], qq[m + 2], qq[m + 3]);
             }
@@ -191,12 +256,6 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK, BOX>& sm,
         } else {
             xsums(buf, [&](int i) -> uint32_t { return xw[i]; });
         }
-    };
-
-    // Value of px (Q = false) or qx (Q = true) at x-pass row `row`, column xq.
-    auto xval = [&](int pb, bool q, int row) -> uint32_t {
-        if constexpr (BOX) return sm.px[pb][row * PXP + xq];
-        else return (q ? sm.qx[pb] : sm.px[pb])[row * PXP + xq];
     };
 
     // y-pass / ring ownership: column xq, rows yg*YO .. yg*YO+YO-1
@@ -211,23 +270,26 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK, BOX>& sm,
     for (int m = 0; m < YO; ++m)
         soff[m] = (xo < g.nx && ybase + m < g.ny) ? voff + (uint32_t)m * rowb : pbytes;
 
-    uint32_t pr[D][YO], qr[D][YO], bacc[YO], wacc[YO];
+    // ring slots of P, Q and G (slice s in slot s mod D) and the running sum
+    uint32_t pr[D][YO], qr[D][YO], gr[D][YO], acc[YO];
 #pragma unroll
     for (int m = 0; m < YO; ++m) {
-        bacc[m] = wacc[m] = 0;
+        acc[m] = 0;
 #pragma unroll
-        for (int u = 0; u < D; ++u) pr[u][m] = qr[u][m] = 0;
+        for (int u = 0; u < D; ++u) pr[u][m] = qr[u][m] = gr[u][m] = 0;
     }
 
-    // The y-pass of the first iteration reads px/qx buffer 1 before any x-pass
-    // wrote it; zeros there push zeros into the (zero) ring, so the loop body
-    // needs no branch.  Likewise the x-pass and the staging run
-    // in every iteration (the extra ones at the end read clamped slices and
-    // their results are never used).  The loop body is then one basic block
-    // the compiler can interleave.
+    // The y-pass of the first iteration reads x-pass buffer 1 before any
+    // x-pass wrote it: zeros there give zero plane sums.  The staging and the
+    // passes run in every iteration (the extra ones at the end read clamped
+    // slices and their results are never stored), so the unrolled block is
+    // one basic block the compiler can interleave.
     for (int i = tid; i < S::LY * PXP; i += S::THREADS) {
         sm.px[1][i] = 0;
-        if constexpr (!BOX) sm.qx[1][i] = 0;
+        if constexpr (MODE == kM9Exact) sm.qx[1][i] = 0;
+    }
+    if constexpr (kCheck) {
+        if (tid == 0) sm.flag = 0;
     }
     const int ns = (z1 - z0) + 2 * H;  // input slices z0-2r .. z1-1+2r
     // the YO stores of output slice zo; zo < 0 stores to an empty buffer
@@ -241,104 +303,146 @@ __device__ __forceinline__ void mean9_tile_body(M9Smem<R, TY, TXW, PK, BOX>& sm,
     // stores so the operation pattern matches the loop's
     stage(z0 - H, 0);
 #pragma unroll
-    for (int p = 1; p < S::PF; ++p) {
-        store_out(-1, bacc);
+    for (int p = 1; p < PF; ++p) {
+        store_out(-1, acc);
         stage(z0 - H + p, p);
     }
     wait_vmem_le<S::VMWAIT>();
     barrier_lds();
-    // iteration k: x-pass of slice k, y-pass of slice k-1, z-window and output
-    // of slice k-2 (the z-window work needs no LDS data, so it runs while the
-    // iteration's LDS reads are in flight)
-    const int nk = ns + 1;
-    for (int kb = 0; kb <= nk; kb += D) {
+    bool ok = true;
+    // iteration k: x-pass of slice k, y-pass of slice k-1 and its outputs;
+    // whole blocks of D iterations (no exit inside the unrolled block)
+    for (int kb = 0; kb <= ns; kb += D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) {
             const int k = kb + u;
-            if (k > nk) break;
-            xload(k % S::NRB);
+            xload(u % NRB);  // slice k, staged PF iterations ago (k mod NRB)
             const int buf = u & 1;  // == k & 1 because D is even
             const int pb = buf ^ 1;
             uint32_t pv[S::NPV], qv[S::NQV];
+            if constexpr (kPQ) {
+                // one word per row: px in the low half, qx in the high half;
+                // the px rows yg*YO+R .. are rows R .. of the qx range
+                uint32_t wv[S::NQV];
 #pragma unroll
-            for (int i = 0; i < S::NPV; ++i) pv[i] = xval(pb, false, yg * YO + R + i);
-            if constexpr (!BOX) {
+                for (int i = 0; i < S::NQV; ++i) wv[i] = sm.px[pb][(yg * YO + i) * PXP + xq];
 #pragma unroll
-                for (int i = 0; i < S::NQV; ++i) qv[i] = xval(pb, true, yg * YO + i);
-            }
-            {
-                // z-window of slice j = k-2, whose P and Q entered the ring in
-                // the previous iteration; it reads slot j+1 (Q of slice j-4r-1)
-                // before the y-pass below overwrites it with slice k-1
-                const int uj = (u + D - 2) % D;
-                uint32_t o[YO];
+                for (int i = 0; i < S::NQV; ++i) qv[i] = wv[i] >> 16;
 #pragma unroll
-                for (int m = 0; m < YO; ++m) {
-                    bacc[m] += pr[(uj + D - R) % D][m] - pr[(uj + R + 1) % D][m];
-                    if constexpr (BOX) {
-                        o[m] = round_div_odd(bacc[m], inv9n);
-                    } else {
-                        wacc[m] += qr[uj][m] - qr[(uj + 1) % D][m];
-                        const uint32_t Ssum = bacc[m] + wacc[m] + qr[(uj + D - 2 * R) % D][m];
-                        o[m] = round_div_odd(Ssum, inv9n);
-                    }
-                    if (GATE && o[m] < gate) o[m] = 0;
+                for (int i = 0; i < S::NPV; ++i) pv[i] = wv[i + R] & 0xffffu;
+            } else {
+#pragma unroll
+                for (int i = 0; i < S::NPV; ++i) pv[i] = sm.px[pb][(yg * YO + R + i) * PXP + xq];
+                if constexpr (MODE == kM9Exact) {
+#pragma unroll
+                    for (int i = 0; i < S::NQV; ++i) qv[i] = sm.qx[pb][(yg * YO + i) * PXP + xq];
                 }
-                store_out((k - 2 >= 2 * H) ? z0 + k - 2 - 2 * H : -1, o);
             }
             {
-                // y-pass of slice k-1 into ring slot k-1
-                const int uy = (u + D - 1) % D;
-                uint32_t cp[S::NPV], cq[S::NQV];
+                // y-pass of slice s = k-1 into ring slot us; slot (us+1) mod D
+                // holds slice s-2r-1, the one that leaves the running sum
+                const int us = (u + D - 1) % D;
+                uint32_t cp[S::NPV], o[YO];
                 cp[0] = pv[0];
 #pragma unroll
                 for (int i = 1; i < S::NPV; ++i) cp[i] = cp[i - 1] + pv[i];
 #pragma unroll
-                for (int m = 0; m < YO; ++m) pr[uy][m] = cp[m + 2 * R] - (m ? cp[m - 1] : 0u);
-                if constexpr (!BOX) {
+                for (int m = 0; m < YO; ++m) pr[us][m] = cp[m + 2 * R] - (m ? cp[m - 1] : 0u);
+                if constexpr (kBox) {
+#pragma unroll
+                    for (int m = 0; m < YO; ++m) {
+                        acc[m] += pr[us][m] - pr[(us + 1) % D][m];
+                        o[m] = round_div_odd(acc[m], inv_div);
+                    }
+                } else {
+                    uint32_t cq[S::NQV];
                     cq[0] = qv[0];
 #pragma unroll
                     for (int i = 1; i < S::NQV; ++i) cq[i] = cq[i - 1] + qv[i];
 #pragma unroll
-                    for (int m = 0; m < YO; ++m)
-                        qr[uy][m] = cq[m + 4 * R] - (m ? cq[m - 1] : 0u) + qv[m + 2 * R];
+                    for (int m = 0; m < YO; ++m) {
+                        qr[us][m] = cq[m + 4 * R] - (m ? cq[m - 1] : 0u) + qv[m + 2 * R];
+                        gr[us][m] = pr[(us + D - R) % D][m] + qr[us][m] + qr[(us + 2) % D][m];
+                        acc[m] += gr[us][m] - gr[(us + 1) % D][m];
+                        o[m] = round_div_odd(acc[m], inv_div);
+                    }
                 }
+#pragma unroll
+                for (int m = 0; m < YO; ++m)
+                    if (GATE && o[m] < gate) o[m] = 0;
+                const int zo = z0 + k - 1 - LAG;
+                store_out((zo >= z0 && zo < z1) ? zo : -1, o);
             }
-            // slice i lives in raw slot i mod NRB: slice k+PF takes the slot
-            // slice k-1 used, read in the previous iteration
-            stage(z0 - H + k + S::PF, (k + S::PF) % S::NRB);
+            // slice k+PF takes the buffer slice k-1 used, read in the previous
+            // iteration
+            stage(z0 - H + k + PF, (u + PF) % NRB);
             xpass(buf);
             wait_vmem_le<S::VMWAIT>();  // slice k+1 has landed
             barrier_lds();
+        }
+        if constexpr (kCheck) {
+            // block end: publish any qx >= 2^16 formed so far, then stop the
+            // whole workgroup if some thread saw one
+            if (qor >> 16) sm.flag = 1;
+            barrier_lds();
+            if (sm.flag) {
+                ok = false;
+                break;
+            }
         }
     }
     // drain the staging of the slices past the end before the LDS is reused
     wait_vmem();
     barrier_lds();
+    return ok;
 }
 
-// LDS for either staging; a kernel that may run both holds the union.
-template <int R, int TY, int TXW = 64, bool BOX = false>
+// Whether packed mode can stop, so that a kernel needs the unpacked bodies.
+template <typename T, int R, bool BOX>
+constexpr bool m9_needs_exact()
+{
+    return !BOX && m9_packed_may_overflow<T, R>();
+}
+
+// LDS of every body a kernel runs: packed (or box) mode with paired and
+// element-wise staging, and the unpacked fallback where packed mode can stop
+// (where it cannot, those members repeat the packed layouts).
+template <int R, int TY, int TXW, typename T, bool BOX = false>
 union M9SmemAny {
-    M9Smem<R, TY, TXW, false, BOX> e;  // element-wise staging
-    M9Smem<R, TY, TXW, true, BOX> p;   // paired staging
+    static constexpr int kMode = BOX ? kM9Box : kM9Packed;
+    static constexpr int kFallback = m9_needs_exact<T, R, BOX>() ? kM9Exact : kMode;
+    M9Smem<R, TY, TXW, true, kMode> p;
+    M9Smem<R, TY, TXW, false, kMode> e;
+    M9Smem<R, TY, TXW, true, kFallback> px;
+    M9Smem<R, TY, TXW, false, kFallback> ex;
 };
 
 // One tile; `pairs` (mean9_pairs_ok for the volume) selects paired staging
-// for the tiles whose x halo stays inside the volume.
+// for the tiles whose x halo stays inside the volume.  MEAN9 runs packed and,
+// where that can stop, again unpacked for a tile whose packed run stopped.
 template <int R, int TY, typename T, bool GATE, int TXW = 64, bool BOX = false>
-__device__ __forceinline__ void mean9_tile(M9SmemAny<R, TY, TXW, BOX>& sm, bool pairs,
+__device__ __forceinline__ void mean9_tile(M9SmemAny<R, TY, TXW, T, BOX>& sm, bool pairs,
                                            const T* __restrict__ in, T* __restrict__ out, Geom g,
                                            int x0, int y0, int z0, int z1, uint32_t gate,
                                            double inv_div)
 {
     constexpr int H = 2 * R, LXE = TXW + 4 * R;
-    if (pairs && x0 - H >= 0 && x0 - H + LXE <= g.nx)
-        mean9_tile_body<R, TY, T, GATE, TXW, true, BOX>(sm.p, in, out, g, x0, y0, z0, z1, gate,
-                                                        inv_div);
-    else
-        mean9_tile_body<R, TY, T, GATE, TXW, false, BOX>(sm.e, in, out, g, x0, y0, z0, z1, gate,
-                                                         inv_div);
+    constexpr int kMode = BOX ? kM9Box : kM9Packed;
+    if (pairs && x0 - H >= 0 && x0 - H + LXE <= g.nx) {
+        if (mean9_tile_body<R, TY, T, GATE, TXW, true, kMode>(sm.p, in, out, g, x0, y0, z0, z1,
+                                                              gate, inv_div))
+            return;
+        if constexpr (m9_needs_exact<T, R, BOX>())
+            mean9_tile_body<R, TY, T, GATE, TXW, true, kM9Exact>(sm.px, in, out, g, x0, y0, z0, z1,
+                                                                 gate, inv_div);
+    } else {
+        if (mean9_tile_body<R, TY, T, GATE, TXW, false, kMode>(sm.e, in, out, g, x0, y0, z0, z1,
+                                                               gate, inv_div))
+            return;
+        if constexpr (m9_needs_exact<T, R, BOX>())
+            mean9_tile_body<R, TY, T, GATE, TXW, false, kM9Exact>(sm.ex, in, out, g, x0, y0, z0,
+                                                                  z1, gate, inv_div);
+    }
 }
 
 }  // namespace lnf

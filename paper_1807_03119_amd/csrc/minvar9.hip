@@ -26,13 +26,18 @@ __attribute__((amdgpu_waves_per_eu(MV9Shape<R, WT>::WAVES))) void minvar9_planes
 }
 
 template <int R, typename T, bool WT>
-hipError_t launch_planes(const void* in, void* out, Geom g, uint32_t gate, int zs, hipStream_t s)
+hipError_t launch_planes(const void* in, void* out, Geom g, uint32_t gate, int zs, hipStream_t s,
+                         TileCfg* plan)
 {
     using S = MV9Shape<R, WT>;
     const int tiles_x = (g.nx + S::TX - 1) / S::TX, tiles_y = (g.ny + S::TY - 1) / S::TY;
     if (zs <= 0)
         zs = default_zs(tiles_x * tiles_y, g.nz,
                         resident_groups((const void*)minvar9_planes<R, T, false, WT>, S::THREADS));
+    if (plan) {
+        plan->zs = zs;
+        return hipSuccess;
+    }
     const int nzs = (g.nz + zs - 1) / zs;
     const int total = tiles_x * tiles_y * nzs;
     const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
@@ -49,26 +54,27 @@ hipError_t launch_planes(const void* in, void* out, Geom g, uint32_t gate, int z
 
 template <int R, typename T>
 hipError_t launch_variant(int variant, const void* in, void* out, Geom g, uint32_t gate, int zs,
-                          hipStream_t s)
+                          hipStream_t s, TileCfg* plan)
 {
-    if (variant == 1) return launch_planes<R, T, true>(in, out, g, gate, zs, s);
-    return launch_planes<R, T, false>(in, out, g, gate, zs, s);
+    if (variant == 1) return launch_planes<R, T, true>(in, out, g, gate, zs, s, plan);
+    return launch_planes<R, T, false>(in, out, g, gate, zs, s, plan);
 }
 
 template <typename T>
 hipError_t dispatch_r(const void* in, void* out, int r, Geom g, uint32_t gate, TileCfg cfg,
-                      hipStream_t s)
+                      hipStream_t s, TileCfg* plan)
 {
     // default variant: the wide tile on large planes where it measured faster
     // (uint16 up to r = 3, uint8 at r = 3), else 32 x 16
     int v = cfg.variant;
     if (v < 0)
         v = (g.nx >= 256 && g.ny >= 256 && r <= 3 && (sizeof(T) == 2 || r == 3)) ? 1 : 0;
+    if (plan) plan->variant = v;
     switch (r) {
-    case 1: return launch_variant<1, T>(v, in, out, g, gate, cfg.zs, s);
-    case 2: return launch_variant<2, T>(v, in, out, g, gate, cfg.zs, s);
-    case 3: return launch_variant<3, T>(v, in, out, g, gate, cfg.zs, s);
-    case 4: return launch_variant<4, T>(v, in, out, g, gate, cfg.zs, s);
+    case 1: return launch_variant<1, T>(v, in, out, g, gate, cfg.zs, s, plan);
+    case 2: return launch_variant<2, T>(v, in, out, g, gate, cfg.zs, s, plan);
+    case 3: return launch_variant<3, T>(v, in, out, g, gate, cfg.zs, s, plan);
+    case 4: return launch_variant<4, T>(v, in, out, g, gate, cfg.zs, s, plan);
     default: return hipErrorInvalidValue;
     }
 }
@@ -91,10 +97,10 @@ void minvar9_tile_shape(int variant, int r, int* tx, int* ty)
 }
 
 hipError_t launch_minvar9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
-                          TileCfg cfg, hipStream_t s)
+                          TileCfg cfg, hipStream_t s, TileCfg* plan)
 {
-    if (dtype == LNF_U8) return dispatch_r<uint8_t>(in, out, r, g, gate, cfg, s);
-    return dispatch_r<uint16_t>(in, out, r, g, gate, cfg, s);
+    if (dtype == LNF_U8) return dispatch_r<uint8_t>(in, out, r, g, gate, cfg, s, plan);
+    return dispatch_r<uint16_t>(in, out, r, g, gate, cfg, s, plan);
 }
 
 }  // namespace lnf
