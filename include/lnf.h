@@ -348,7 +348,10 @@ LNF_API int lnf_server_release(lnf_server_handle srv, uint64_t vol_id);
  * Queue a filter request: filter resident volume vol_id at `radius`.  If
  * host_out is not NULL the result is copied there (dense layout, included in
  * the latency).  arrival_ns: scheduled arrival on lnf_server_now_ns's clock;
- * 0 = now.  Errors: LNF_EINVAL, LNF_ENOTFOUND.
+ * 0 = now.  Errors: LNF_EINVAL, LNF_ENOTFOUND, LNF_EBUSY (the volume and its
+ * output together exceed the cap, so the request could never run).  A queued
+ * request that cannot get memory for its output while nothing else runs or
+ * waits to run (every idle volume evicted) ends with status LNF_EBUSY.
  */
 LNF_API int lnf_server_submit(lnf_server_handle srv, uint64_t vol_id, int radius, void* host_out,
                               int64_t arrival_ns, uint64_t* ticket);

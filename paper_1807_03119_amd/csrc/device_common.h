@@ -122,13 +122,18 @@ __device__ __forceinline__ void wait_vmem_le()
     asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-// round(S / d) for an odd divisor d, as trunc(S * (1/d) + 1/2) in fp64.
-// (2S + d) / (2d) is never an integer (odd over even), so it lies at least
-// 1/(2d) from every integer, while the fp64 error is below 2^-52 * S/d; with
-// S < 2^30 and d < 2^14 the truncation is therefore exact.
+// round(S / d) for an odd divisor d < 2^20, in two instructions: one fp64
+// fma forms S * (1/d) + 2^52 with a single rounding.  Between 2^52 and 2^53
+// the fp64 spacing is 1, so that rounding is to the nearest integer, and the
+// low 32 bits of the result's encoding are that integer (the mantissa of
+// 2^52 + q is q).  S/d is never a half-integer (odd d), so it lies at least
+// 1/(2d) from every rounding boundary, while S * fl(1/d) differs from S/d by
+// less than S/d * 2^-53 < 2^-21 <= 1/(2d) for S < 2^32: the nearest integer
+// of S * fl(1/d) is the correctly rounded S/d.
 __device__ __forceinline__ uint32_t round_div_odd(uint32_t s, double inv_d)
 {
-    return (uint32_t)__builtin_fma((double)s, inv_d, 0.5);
+    const double t = __builtin_fma((double)s, inv_d, 4503599627370496.0);  // + 2^52
+    return (uint32_t)__builtin_bit_cast(uint64_t, t);
 }
 
 }  // namespace lnf

@@ -296,6 +296,10 @@ public:
         auto it = vols_.find(vid);
         if (it == vols_.end() || it->second.released) return LNF_ENOTFOUND;
         Volume& v = it->second;
+        // the volume and this request's output must fit under the cap together,
+        // else the request could never be admitted
+        const size_t vbytes = (size_t)v.dims[0] * v.dims[1] * v.dims[2] * (v.dtype == LNF_U8 ? 1 : 2);
+        if (Arena::round(vbytes) + Arena::round(vbytes) > o_.cap_bytes) return LNF_EBUSY;
         v.refs += 1;
         touch(vid, v);
         Request r;
@@ -347,6 +351,8 @@ public:
         if (it->second.state != kPending) return LNF_EBUSY;
         pending_.erase(std::find(pending_.begin(), pending_.end(), t));
         finish(t, LNF_ECANCELED, 0);
+        lk.unlock();
+        done_cv_.notify_all();
         return LNF_OK;
     }
 
@@ -510,7 +516,16 @@ private:
             Request& r = reqs_[t];
             const Volume& v = vols_[r.vol];
             const size_t bytes = (size_t)r.voxels * (v.dtype == LNF_U8 ? 1 : 2);
-            if (get_block(bytes, r.vol, &r.out, &r.block) != LNF_OK) break;  // wait for memory
+            if (get_block(bytes, r.vol, &r.out, &r.block) != LNF_OK) {
+                // Nothing in flight or admitted in this pass will free memory
+                // and every idle volume is already evicted: the request cannot
+                // be admitted now, nor later.  End it so the queue moves on.
+                if (!flights_.empty() || !got.empty()) break;  // wait for memory
+                pending_.pop_front();
+                finish(t, LNF_EBUSY, steady_ns(), true);
+                done_cv_.notify_all();
+                continue;
+            }
             r.state = kInFlight;
             pending_.pop_front();
             got.push_back(t);

@@ -167,3 +167,60 @@ def test_continuous_batching_groups_requests():
         st = s.stats()
         assert st["completed"] == 40
         assert st["batches"] < 40  # requests that queued up were launched together
+
+
+def test_requests_that_cannot_fit_end_with_ebusy():
+    """A volume whose output would not fit beside it under the cap is refused at
+    submit; requests whose own volumes fill the cap end with LNF_EBUSY instead
+    of waiting forever (the queue moves on and sync returns)."""
+    import threading
+    cap = 3 << 20
+    with _filter() as f, _server(f, cap_bytes=cap, max_batch=4) as s:
+        big = ph.ct_u12((128, 128, 64), seed=21)            # 2 MiB: 2 + 2 > 3 MiB
+        rc, vid = s.put(_pinned(big))
+        assert rc == 0
+        assert s.submit(vid, 1)[0] == _lib.LNF_EBUSY
+        assert s.release(vid) == 0
+        half = ph.ct_u12((128, 96, 64), seed=22)            # 1.5 MiB each: both fill the cap
+        rc_a, a = s.put(_pinned(half))
+        rc_b, b = s.put(_pinned(half))
+        assert rc_a == 0 and rc_b == 0
+        tickets = []
+        for vid in (a, b):
+            rc, t = s.submit(vid, 1)
+            assert rc in (0, _lib.LNF_ENOTFOUND)            # b may already be evicted
+            if rc == 0:
+                tickets.append(t)
+        done = threading.Event()
+        threading.Thread(target=lambda: (s.sync(), done.set()), daemon=True).start()
+        assert done.wait(30), "server sync did not return"
+        for t in tickets:
+            assert s.wait(t, 1000) in (0, _lib.LNF_EBUSY)
+        assert s.stats()["peak_bytes"] <= cap
+
+
+def test_cancel_wakes_a_waiting_thread():
+    """lnf_server_wait on a ticket returns as soon as another thread cancels it."""
+    import threading
+    import time
+    # requests that take longer to run than to submit, so the queue builds up
+    vol = np.random.default_rng(23).integers(0, 4096, (256, 256, 256), dtype=np.uint16)
+    with _filter() as f, _server(f, mode=_lib.LNF_SERVE_FIFO) as s:
+        rc, vid = s.put(_pinned(vol))
+        assert rc == 0
+        for attempt in range(5):
+            tickets = [s.submit(vid, 4)[1] for _ in range(96)]
+            last = tickets[-1]
+            res = {}
+            th = threading.Thread(target=lambda: res.setdefault("rc", s.wait(last, -1)), daemon=True)
+            th.start()
+            time.sleep(0.001)
+            rc = s.cancel(last)
+            th.join(20)
+            assert not th.is_alive(), "waiter not woken"
+            s.sync()
+            if rc == 0:
+                assert res["rc"] == _lib.LNF_ECANCELED
+                return
+            assert rc == _lib.LNF_EBUSY and res["rc"] == 0  # it had already started
+        pytest.skip("the request always started before it could be cancelled")
