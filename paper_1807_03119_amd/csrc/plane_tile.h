@@ -365,12 +365,14 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
         }
     };
 
-    const int npl = (z1 - z0) + 2 * D;  // centre planes z0-D .. z1-1+D
+    // centre planes z0-D .. z1-1+D, in whole blocks of U (no exit inside the
+    // unrolled block); the planes past the end read clamped slices and store
+    // nothing
+    const int npl = (z1 - z0) + 2 * D;
     for (int qb = 0; qb < npl; qb += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int q = qb + u;
-            if (q >= npl) break;
             const int p = p0 + q;
             // 1. z-sums of plane p (en = slice p+r, eo = slice p-r-1 or zeros)
 #pragma unroll
@@ -488,7 +490,7 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
             //    output p - D
             const int ur = (u + U - D % U) % U;  // slot written D planes ago
             const rsrc_t wr = make_rsrc(out + (size_t)max(p - D, 0) * plane,
-                                        q >= 2 * D ? pbytes : 0u);
+                                        (q >= 2 * D && q < npl) ? pbytes : 0u);
 #pragma unroll
             for (int j = 0; j < OPT; ++j) {
                 const int oy = oyb + j * S::OROWS;
