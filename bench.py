@@ -22,14 +22,52 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
+# VALU peak in 32-bit lane operations per second: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz (the MINVAR9 kernel is bound by its VALU work, not by HBM)
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 DIMS = (512, 512, 512)
 SEED = 2000
-# Measured HBM bytes per launch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, each
-# scaled by what it reads for the device copy of known size that this script
-# times), per (rule, radius), for the kernels as they stand; the summaries with
-# the commands are profiles/mean9_stream_r3_512cube_u16.txt and
-# profiles/minvar9_planes_r3_512cube_u16.txt.  Absent: not measured.
-TRAFFIC_BYTES = {("mean9", 3): 649755164, ("minvar9", 3): 615475061}
+# rocprofv3 summaries of the kernels this script times (512^3 uint16, r = 3),
+# with the measured HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, each scaled
+# by what it reads for the device copy of known size this script times) and the
+# VALU lane operations per voxel.  Each records a hash of the kernel's sources;
+# a figure is used only while the sources still hash the same (else null).
+PROFILES = {
+    "mean9": ("profiles/mean9_stream_r3_512cube_u16.txt",
+              ["mean9.hip", "mean9_tile.h", "device_common.h", "lnf_internal.h"]),
+    "minvar9": ("profiles/minvar9_planes_r3_512cube_u16.txt",
+                ["minvar9.hip", "minvar9_tile.h", "plane_tile.h", "device_common.h",
+                 "lnf_internal.h"]),
+}
+
+
+def sources_sha256(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1807_03119_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled(rule):
+    """(traffic bytes per launch, VALU lane ops per voxel) from the committed
+    profile of `rule`'s kernel, or (None, None) if the kernel changed since."""
+    path, files = PROFILES[rule]
+    vals = {}
+    try:
+        with open(os.path.join(ROOT, path)) as fh:
+            for line in fh:
+                k, _, v = line.strip().partition(":")
+                if k in ("sources_sha256", "traffic_bytes_per_launch", "valu_lane_ops_per_voxel"):
+                    vals[k] = v.strip()
+    except OSError:
+        return None, None
+    if vals.get("sources_sha256") != sources_sha256(files):
+        return None, None
+    t = vals.get("traffic_bytes_per_launch")
+    v = vals.get("valu_lane_ops_per_voxel")
+    return (int(t) if t else None), (float(v) if v else None)
 
 
 def log(msg):
@@ -64,28 +102,73 @@ def copy_bandwidth(nbytes, stream):
 
 def batch_benchmark(rule_code, stream, steps=5):
     """64 mixed volumes (axes 64..384, uint8/uint16, r in 1..3): one batch call
-    of the batch path against one tuned launch per volume on the same stream."""
+    as a per-tile grid, as a persistent tile queue, and the grid call captured
+    in a HIP graph and replayed, against one tuned launch per volume, all on
+    the same stream.  Every mode's bytes are checked against the singles."""
     import torch
-    from paper_1807_03119_amd import phantom
+    from paper_1807_03119_amd import _lib, phantom
     from paper_1807_03119_amd.api import Filter
     jobs = phantom.batch_jobs()
     vols = [phantom.batch_volume(j, device="cuda") for j in jobs]
     outs = [torch.empty_like(v) for v in vols]
+    ref = [torch.empty_like(v) for v in vols]
     nvox = sum(v.numel() for v in vols)
     nbytes = sum(2 * v.numel() * v.element_size() for v in vols)
     f = Filter(rule_code, 0)
     f.tune([(v, o, j.radius) for v, o, j in zip(vols, outs, jobs)])
     triples = [(v, o, j.radius) for v, o, j in zip(vols, outs, jobs)]
-    ms_b, _ = time_launches(lambda: f.batch(triples), steps, 2, stream)
 
     def singles():
-        for v, o, j in zip(vols, outs, jobs):
+        for v, o, j in zip(vols, ref, jobs):
             f(v, j.radius, out=o)
     ms_s, _ = time_launches(singles, steps, 2, stream)
+
+    def same():
+        torch.cuda.synchronize()
+        return all(torch.equal(a.view(torch.uint8), b.view(torch.uint8)) for a, b in zip(outs, ref))
+    res = {"jobs": len(jobs), "voxels": nvox, "singles_ms": ms_s,
+           "singles_Gvox_s": nvox / (ms_s * 1e-3) / 1e9}
+    for name, mode in (("grid", _lib.LNF_BATCH_GRID), ("queue", _lib.LNF_BATCH_PERSISTENT)):
+        for o in outs:
+            o.zero_()
+        ms, _ = time_launches(lambda: f.batch(triples, mode=mode), steps, 2, stream)
+        res[f"{name}_ms"] = ms
+        res[f"{name}_Gvox_s"] = nvox / (ms * 1e-3) / 1e9
+        res[f"{name}_GBps"] = nbytes / (ms * 1e-3) / 1e9
+        res[f"{name}_bytes_equal_singles"] = same()
     f.close()
-    return {"jobs": len(jobs), "voxels": nvox, "batch_ms": ms_b, "singles_ms": ms_s,
-            "batch_Gvox_s": nvox / (ms_b * 1e-3) / 1e9, "singles_Gvox_s": nvox / (ms_s * 1e-3) / 1e9,
-            "batch_GBps": nbytes / (ms_b * 1e-3) / 1e9}
+    # the grid call captured once in a graph (a context of its own, so no
+    # earlier call left a table slot pending), replayed `steps` times
+    try:
+        g = Filter(rule_code, 0)
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            g.batch(triples)
+        graph.replay()
+        ok = same()
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        cur = torch.cuda.current_stream()
+        start.record(cur)
+        for _ in range(steps):
+            graph.replay()
+        stop.record(cur)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / steps
+        ok = ok and same()
+        res.update({"graph_ms": ms, "graph_Gvox_s": nvox / (ms * 1e-3) / 1e9,
+                    "graph_bytes_equal_singles": ok})
+        del graph
+        g.close()
+    except Exception as e:  # capture unsupported: report, do not fail the run
+        res["graph_error"] = f"{type(e).__name__}: {e}"[:200]
+    res["grid_vs_singles"] = ms_s / res["grid_ms"]
+    res["queue_vs_singles"] = ms_s / res["queue_ms"]
+    return res
 
 
 def serve_benchmark(rule_code, seconds, rate=300.0, pool_n=8, side=512):
@@ -161,6 +244,71 @@ def serve_benchmark(rule_code, seconds, rate=300.0, pool_n=8, side=512):
     return out
 
 
+def serve_sweep(rule_code, rates=(300, 1000, 3000, 10000, 20000), seconds=1.5, n_vols=24,
+                max_requests=20000):
+    """Open-loop Poisson re-filter requests on device-resident volumes (no
+    upload in the loop): cube sides log-uniform 128..512, r in 1..3, at each
+    rate, served with continuous batching and with one launch per request in
+    FIFO order.  Reports p50/p99 latency (from the scheduled arrival) and the
+    served rate; the load where batching starts to win is where FIFO's queue
+    grows."""
+    import math
+
+    import numpy as np
+    import torch
+    from paper_1807_03119_amd import _lib, phantom
+    from paper_1807_03119_amd.api import Filter, Server
+    rng = np.random.default_rng(5700)
+    sides = [int(round(math.exp(rng.uniform(math.log(128), math.log(512))))) for _ in range(n_vols)]
+    hosts = []
+    for i, sd in enumerate(sides):
+        v = phantom.ct_u12((sd, sd, sd), seed=5800 + i, device="cuda")
+        hbuf = torch.empty(v.shape, dtype=torch.uint16, pin_memory=True)
+        hbuf.copy_(v)
+        hosts.append(hbuf)
+        del v
+    torch.cuda.synchronize()
+    out = {"volumes": n_vols, "voxels_per_volume_mean": float(np.mean([sd ** 3 for sd in sides])),
+           "seconds_per_rate": seconds, "rates": {}}
+    for rate in rates:
+        n = min(max_requests, int(rate * seconds))
+        gaps = rng.exponential(1.0 / rate, n)
+        arrivals = np.cumsum(gaps)
+        picks = rng.integers(0, n_vols, n)
+        radii = rng.integers(1, 4, n)
+        vox = float(sum(sides[int(i)] ** 3 for i in picks))
+        row = {"requests": n, "offered_Gvox_s": vox / float(arrivals[-1]) / 1e9}
+        for name, mode in (("batched", _lib.LNF_SERVE_BATCHED), ("fifo", _lib.LNF_SERVE_FIFO)):
+            f = Filter(rule_code, 0)
+            srv = Server(f, n_streams=4, max_batch=256, mode=mode)
+            ids = [srv.put(h)[1] for h in hosts]
+            srv.sync()
+            srv.stats(reset=True)
+            t0 = _lib.lnf_server_now_ns() + 50_000_000
+            lag = 0.0
+            for k in range(n):
+                due = t0 + int(arrivals[k] * 1e9)
+                while True:
+                    now = _lib.lnf_server_now_ns()
+                    if now >= due:
+                        break
+                    if due - now > 1_000_000:
+                        time.sleep((due - now - 500_000) * 1e-9)
+                lag = max(lag, (now - due) * 1e-6)
+                srv.submit(ids[int(picks[k])], int(radii[k]), arrival_ns=due)
+            srv.sync()
+            st = srv.stats()
+            row[name] = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "max_ms": st["max_ms"],
+                         "served_Gvox_s": st["gvox_per_s"], "batches": st["batches"],
+                         "completed": st["completed"], "client_lag_max_ms": lag}
+            srv.close()
+            f.close()
+        out["rates"][str(rate)] = row
+        log(f"  sweep {rate}/s: batched p99 {row['batched']['p99_ms']:.2f} ms, "
+            f"fifo p99 {row['fifo']['p99_ms']:.2f} ms")
+    return out
+
+
 def burst_benchmark(rule_code, n_vols=32, n_req=2048, side_lo=48, side_hi=160):
     """Closed burst: n_req re-filter requests on resident volumes submitted at
     once (sides log-uniform in [side_lo, side_hi], r in 1..3), served with
@@ -204,34 +352,69 @@ def burst_benchmark(rule_code, n_vols=32, n_req=2048, side_lo=48, side_hi=160):
     return out
 
 
-def cpu_baseline(vol_np, radius, rule, got_np, budget_s=12.0):
-    """Time the oracle on whole z-slices of the same volume; verify them too."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(vol_np, radius, rule, got_np, budget_s=12.0, single_s=4.0):
+    """Time the oracle on whole z-slices of the same volume, on all host threads
+    and on one; verify the slices against the GPU output too."""
     import numpy as np
     import oracle
     nz, ny, nx = vol_np.shape
     orule = oracle.MEAN9 if rule == "mean9" else oracle.MINVAR9
 
-    def run(z0, k):
-        zz, yy, xx = np.meshgrid(np.arange(z0, z0 + k), np.arange(ny), np.arange(nx),
+    def run(z0, k, rows=None):
+        rows = ny if rows is None else rows
+        zz, yy, xx = np.meshgrid(np.arange(z0, z0 + k), np.arange(rows), np.arange(nx),
                                  indexing="ij")
         pts = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], 1)
         t = time.perf_counter()
         vals = oracle.filter_points(vol_np, radius, pts, orule)
         dt = time.perf_counter() - t
-        ok = np.array_equal(vals, got_np[z0:z0 + k].ravel().astype(np.uint32))
+        ok = np.array_equal(vals, got_np[z0:z0 + k, :rows].ravel().astype(np.uint32))
         return dt, ok
 
+    threads = oracle.threads()
     z0 = nz // 2
     dt1, ok1 = run(z0, 1)
     k = int(max(1, min(nz - z0 - 1, budget_s / max(dt1, 1e-6))))
     dt, ok = run(z0 + 1, k)
     vox = k * ny * nx
+    # one thread: rows of one slice, about single_s seconds
+    oracle.set_threads(1)
+    try:
+        dr, okr = run(z0, 1, rows=8)
+        rows = int(max(8, min(ny, single_s / max(dr, 1e-6) * 8)))
+        ds, oks = run(z0, 1, rows=rows)
+    finally:
+        oracle.set_threads(threads)
     return {
-        "value": vox / dt / 1e9, "unit": "Gvoxel/s", "cores": oracle.threads(), "kind": "oracle",
+        "value": vox / dt / 1e9, "unit": "Gvoxel/s", "cores": threads, "kind": "oracle",
         "sample": f"{k} whole z-slices ({vox} voxels) of the same {nx}x{ny}x{nz} volume, "
-                  f"brute-force oracle, r={radius}, {rule.upper()}; took {dt:.1f} s",
-        "sample_matches_gpu": bool(ok and ok1),
+                  f"brute-force oracle, r={radius}, {rule.upper()}, {threads} threads; took {dt:.1f} s",
+        "single_core": {"value": rows * nx / ds / 1e9, "unit": "Gvoxel/s", "cores": 1,
+                        "sample": f"{rows} rows of one z-slice ({rows * nx} voxels); took {ds:.1f} s"},
+        "cpu_model": cpu_model(),
+        "sample_matches_gpu": bool(ok and ok1 and okr and oks),
     }
+
+
+def valu_info(gvox, lane_ops):
+    """The kernel against its VALU bound: lane operations per voxel (profiled)
+    and the voxel rate at 100 % VALU issue."""
+    if not lane_ops:
+        return None
+    bound = VALU_PEAK_LANE_OPS / lane_ops / 1e9
+    return {"lane_ops_per_voxel": lane_ops, "bound_Gvox_s": bound, "frac": gvox / bound}
 
 
 def main():
@@ -273,7 +456,7 @@ def main():
     gvox = nvox / (ms * 1e-3) / 1e9
     alg_bytes = 4 * nvox  # read + write of one uint16 per voxel
     achieved = alg_bytes / (ms * 1e-3) / 1e9
-    traffic = TRAFFIC_BYTES.get((args.rule, args.radius))
+    traffic, lane_ops = profiled(args.rule) if args.radius == 3 else (None, None)
     res = {
         "metric": "filtered Gvoxel/s + % of HBM roofline; p50/p99 latency in served mode",
         "value": gvox, "unit": "Gvoxel/s", "n_gpus": 1, "steps": args.steps,
@@ -285,6 +468,7 @@ def main():
                    "rule": args.rule.upper(), "seed": SEED},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "valu": valu_info(gvox, lane_ops),
         "timed_wall_s": wall,
     }
     torch.cuda.synchronize()
@@ -300,6 +484,11 @@ def main():
                     continue
                 ms2, _ = time_launches(lambda: g(vol, r, out=out), 10, 2, stream)
                 extras[f"{rule_name}_r{r}_Gvox_s"] = nvox / (ms2 * 1e-3) / 1e9
+                if r == 3:
+                    gv = nvox / (ms2 * 1e-3) / 1e9
+                    t3, ops3 = profiled(rule_name)
+                    extras[f"{rule_name}_r3"] = {"Gvox_s": gv, "hbm_frac": gv * 4 / HBM_PEAK_GBS,
+                                                 "valu": valu_info(gv, ops3)}
             g.close()
         log("timing the cluster geometry variants")
         geoms = {"box_d1": _lib.LNF_GEOM_OFFSET_1, "box_d2r1": _lib.LNF_GEOM_OFFSET_2R1,
@@ -361,14 +550,17 @@ def main():
             extras["points"][f"{rule_name}_r{args.radius}_ms"] = ms2
             extras["points"][f"{rule_name}_r{args.radius}_Mpoints_s"] = npts / (ms2 * 1e-3) / 1e6
             g.close()
-        log("timing the 64-volume mixed batch")
-        extras["batch64"] = batch_benchmark(rule_code, stream)
+        log("timing the 64-volume mixed batch, both rules")
+        extras["batch64"] = {name: batch_benchmark(rc, stream)
+                             for name, rc in (("mean9", _lib.LNF_MEAN9), ("minvar9", _lib.LNF_MINVAR9))}
         res["extras"] = extras
         if args.serve_seconds > 0:
             log(f"serving trace: {args.serve_seconds:.0f} s at 300 req/s, batched then FIFO")
             res["served"] = serve_benchmark(rule_code, args.serve_seconds)
             log("serving burst of small re-filter requests")
             res["served"]["burst"] = burst_benchmark(rule_code)
+            log("serving rate sweep on resident volumes")
+            res["served"]["sweep"] = serve_sweep(rule_code)
     if not args.no_cpu_baseline:
         f(vol, args.radius, out=out)
         torch.cuda.synchronize()

@@ -99,8 +99,9 @@ typedef struct {
 
 /*
  * Create a filter context.  opt == NULL gives the defaults (LNF_MEAN9, gate off,
- * current device).  Allocates only library-internal state (a few KB of device
- * memory for the batch descriptor table and the histogram scratch).
+ * current device).  Allocates only library-internal state: eight job-table
+ * slots of lnf_filter_batch (about 200 KB of device memory and 200 KB of pinned
+ * host memory each), and later the histogram and entropy scratch.
  * Errors: LNF_EINVAL (h NULL, bad rule, unknown or conflicting flags, size), LNF_EDEVICE (bad device),
  * LNF_ENOMEM, LNF_EHIP.
  */
@@ -168,18 +169,38 @@ typedef struct {
 #define LNF_BATCH_MAX 4096 /* most jobs one lnf_filter_batch call accepts */
 
 /*
- * Filter n volumes with the context's rule and gate in one call: the jobs are
- * grouped by (radius, dtype), and each group runs as ONE kernel launch over the
- * tiles of all its volumes (larger volumes first), after one copy of the job
- * table; everything is enqueued on `stream`.  Each output is byte-identical to
+ * Filter n volumes with the context's rule, geometry and gate in one call: the
+ * jobs are grouped by (radius, dtype), and each group runs as ONE kernel launch
+ * over the tiles of all its volumes (larger volumes first), after one copy of
+ * the job table; everything is enqueued on `stream`.  Each output is byte-identical to
  * lnf_filter on the same job.  The job table is copied by the call, so `jobs`
  * may be reused as soon as it returns; the buffers must stay valid until the
  * work completes on `stream`.  n == 0 is a no-op.
+ * A call may be captured in a HIP graph (stream capture): it then takes one of
+ * four job-table slots kept for captures for the context's lifetime, since each
+ * replay copies that table again; a fifth capture on one context returns
+ * LNF_EBUSY.  Calls that are not captured take the other slots in turn.
  * Errors: LNF_EINVAL (n < 0 or > LNF_BATCH_MAX, a bad job, jobs whose outputs
- * overlap any input or output), LNF_EDEVICE, LNF_ENOMEM, LNF_EHIP.  Argument
- * errors are found before anything is enqueued.
+ * overlap any input or output), LNF_EDEVICE, LNF_ENOMEM, LNF_EHIP, LNF_EBUSY.
+ * Argument errors are found before anything is enqueued.
  */
 LNF_API int lnf_filter_batch(lnf_handle h, const lnf_job* jobs, int n, hipStream_t stream);
+
+#define LNF_BATCH_GRID 0       /* one workgroup per tile, hardware-dispatched (default) */
+#define LNF_BATCH_PERSISTENT 1 /* one workgroup per resident slot, tiles from a queue */
+
+/*
+ * lnf_filter_batch with an explicit launch mode; both modes give the same
+ * bytes.  LNF_BATCH_PERSISTENT launches, per group, as many workgroups as the
+ * GPU holds at once, and each takes tiles from an atomic counter in the job
+ * table until the group is done (MEAN9 with 64 x 16 tiles, MINVAR9 with its
+ * tuned or default tile).  The counters are uploaded as zero with the table,
+ * so both modes can be captured in a HIP graph (no memset node).  Default
+ * cluster geometry only.  Errors: as lnf_filter_batch; LNF_EINVAL also for an
+ * unknown mode, or LNF_BATCH_PERSISTENT on a context with LNF_GEOM_* flags.
+ */
+LNF_API int lnf_filter_batch_mode(lnf_handle h, const lnf_job* jobs, int n, hipStream_t stream,
+                                  int mode);
 
 /*
  * Autotune: for every distinct (dtype, radius, volume-size class) among the

@@ -63,6 +63,8 @@ def _load():
     lib.lnfo_cluster_stats.argtypes = [vp, i64, i64, i64, ctypes.c_int, ctypes.c_int,
                                        i64, i64, i64, vp, vp]
     lib.lnfo_threads.argtypes = []
+    lib.lnfo_set_threads.argtypes = [ctypes.c_int]
+    lib.lnfo_set_threads.restype = None
     for f in (lib.lnfo_filter, lib.lnfo_filter_geom, lib.lnfo_filter_points,
               lib.lnfo_cluster_stats, lib.lnfo_cluster_stats_geom, lib.lnfo_threads):
         f.restype = ctypes.c_int
@@ -121,3 +123,8 @@ def cluster_stats(vol: np.ndarray, r: int, x: int, y: int, z: int, shape: int = 
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().lnfo_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's parallel loops on n threads from now on."""
+    _load().lnfo_set_threads(int(n))

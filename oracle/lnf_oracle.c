@@ -264,6 +264,17 @@ int lnfo_threads(void)
     return t;
 }
 
+/* Use n OpenMP threads in the parallel regions that follow (n >= 1). */
+void lnfo_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n < 1 ? 1 : n);
+#else
+    (void)n;
+#endif
+}
+
 /* ---- comparison filters (paper, Section "Other Filters") -------------------
  * TEST INFRASTRUCTURE ONLY, like everything in this file.  Readings where the
  * paper's formulas are garbled or silent (each filter starts from the same

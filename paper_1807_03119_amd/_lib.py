@@ -55,6 +55,8 @@ class lnf_job(ctypes.Structure):
 
 
 LNF_BATCH_MAX = 4096
+LNF_BATCH_GRID = 0
+LNF_BATCH_PERSISTENT = 1
 LNF_SERVE_BATCHED = 0
 LNF_SERVE_FIFO = 1
 
@@ -89,6 +91,7 @@ def _declare(lib):
         "lnf_tile_variants": [_i32, _i32, _i32],
         "lnf_tile_config": [_vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, ctypes.POINTER(lnf_tile)],
         "lnf_filter_batch": [_vp, ctypes.POINTER(lnf_job), _i32, _vp],
+        "lnf_filter_batch_mode": [_vp, ctypes.POINTER(lnf_job), _i32, _vp, _i32],
         "lnf_tune": [_vp, ctypes.POINTER(lnf_job), _i32],
         "lnf_tune_save": [_vp, ctypes.c_char_p],
         "lnf_tune_load": [_vp, ctypes.c_char_p],
@@ -265,13 +268,16 @@ def make_jobs(items):
     return arr
 
 
-def lnf_filter_batch(h, jobs, n=None, stream=None) -> int:
-    """`jobs`: a make_jobs array (or a list accepted by make_jobs)."""
+def lnf_filter_batch(h, jobs, n=None, stream=None, mode=None) -> int:
+    """`jobs`: a make_jobs array (or a list accepted by make_jobs); mode None
+    calls lnf_filter_batch, else lnf_filter_batch_mode."""
     if isinstance(jobs, (list, tuple)):
         n = len(jobs) if n is None else n
         jobs = make_jobs(jobs)
     n = len(jobs) if n is None else n
-    return lib().lnf_filter_batch(h, jobs, n, stream_ptr(stream))
+    if mode is None:
+        return lib().lnf_filter_batch(h, jobs, n, stream_ptr(stream))
+    return lib().lnf_filter_batch_mode(h, jobs, n, stream_ptr(stream), int(mode))
 
 
 def lnf_tune(h, jobs, n=None) -> int:

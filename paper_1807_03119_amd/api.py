@@ -117,9 +117,10 @@ class Filter:
             raise LnfError(rc, "lnf_histogram")
         return hist
 
-    def batch(self, items, stream=None):
+    def batch(self, items, stream=None, mode=None):
         """Filter [(vol, radius), ...] (or [(vol, out, radius), ...]) with one
-        launch per (radius, dtype) group; returns the list of outputs."""
+        launch per (radius, dtype) group; returns the list of outputs.  mode:
+        LNF_BATCH_GRID (None: the default) or LNF_BATCH_PERSISTENT."""
         import torch
         triples = []
         for it in items:
@@ -130,7 +131,7 @@ class Filter:
                 vol, out, r = it
             _require_cuda(vol, "vol")
             triples.append((vol, out, r))
-        rc = _lib.lnf_filter_batch(self._h, triples, stream=stream)
+        rc = _lib.lnf_filter_batch(self._h, triples, stream=stream, mode=mode)
         if rc != _lib.LNF_OK:
             raise LnfError(rc, "lnf_filter_batch")
         return [t[1] for t in triples]

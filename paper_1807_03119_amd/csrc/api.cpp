@@ -167,7 +167,11 @@ TuneKey tune_key(int rule, int dtype, int radius, Geom g)
 int ctx_init_device_state(lnf_ctx* c)
 {
     c->dev_state = nullptr;
-    return LNF_OK;
+    DeviceGuard dg(c->device);
+    if (!dg.ok()) return LNF_EHIP;
+    const int rc = batch_state_init(c);
+    if (rc != LNF_OK) batch_state_free(c);
+    return rc;
 }
 
 void ctx_free_device_state(lnf_ctx* c)

@@ -1,20 +1,24 @@
 // Batched filtering: many volumes of mixed size, dtype and radius in one call.
 //
 // The jobs are grouped into classes of equal (radius, voxel type).  Each class
-// runs as ONE kernel launch over the tiles of all its volumes: workgroup b
-// takes tile b of the class (XCD-aware order), finds its volume by binary
-// search over the jobs' first-tile indices, and runs the same streaming tile
-// body as the single-volume kernels (same registers, same occupancy).  The
-// hardware dispatcher then keeps the GPU full across volume boundaries, and a
-// class pays one launch and one tail instead of one per volume.  Larger
-// volumes come first in a class, so its tail consists of small tiles.
+// runs as ONE kernel launch over the tiles of all its volumes, in one of two
+// modes:
+//   - grid (LNF_BATCH_GRID, the default): workgroup b takes tile b of the class
+//     (XCD-aware order), finds its volume by binary search over the jobs'
+//     first-tile indices, and runs the same tile body as the single-volume
+//     kernels (same registers, same occupancy).  Larger volumes come first, so
+//     the class's tail consists of small tiles;
+//   - queue (LNF_BATCH_PERSISTENT): one workgroup per resident slot takes tiles
+//     from an atomic counter in the job table until the class is done.
+// The hardware dispatcher (grid) or the queue keeps the GPU full across volume
+// boundaries, and a class pays one launch and one tail instead of one per
+// volume.  Geometry-variant contexts run the cluster kernel of cluster.hip the
+// same way (grid mode).
 //
 // Per call: one H2D copy of the job table (from one of four pinned staging
-// slots) and one launch per non-empty class, all on the caller's stream.
-// These are plain launches rather than a graph: with this runtime a graph of a
-// copy and one kernel costs about 15 us per launch and parallel kernel
-// branches 45-95 us, against about 5 us for the copy and a kernel launched
-// directly.
+// slots, queue counters uploaded as zero, so the call can be captured in a
+// graph without memset nodes) and one launch per non-empty class, all on the
+// caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,148 +32,108 @@
 #include "device_common.h"
 #include "lnf_ctx.h"
 #include "lnf_internal.h"
+#include "batch_table.h"
 #include "mean9_tile.h"
 #include "minvar9_tile.h"
 
 namespace lnf {
 
-struct BatchJobDesc {
-    const void* in;
-    void* out;
-    int nx, ny, nz;
-    int tiles_x, tiles_y, zs, tile_begin;  // tile_begin: first tile in its class
-    int pairs;                             // MEAN9 stages element pairs (mean9_pairs_ok)
-};
-
-struct BatchClass {
-    int total;      // tiles in this class
-    int njobs;      // jobs in this class
-    int job_begin;  // index of its first job in `jobs`
-    int variant;    // MEAN9 tile variant of the class
-};
-
-constexpr int kClasses = 2 * LNF_RADIUS_MAX;  // (radius, voxel type)
-
-// Class of a (radius, dtype) pair.
-constexpr int batch_class(int r, int dtype) { return 2 * (r - 1) + (dtype == LNF_U16 ? 1 : 0); }
-
-struct BatchTable {
-    BatchClass c[kClasses];
-    BatchJobDesc jobs[LNF_BATCH_MAX];
-};
-
 namespace {
 
-constexpr int kSlots = 4;
+constexpr int kSlots = 4;         // job-table staging slots of eager calls, used in turn
+constexpr int kCaptureSlots = 4;  // slots of calls captured in a graph, one per capture
 
-// Job of class tile t: the last job whose first tile is <= t (uniform per
-// workgroup, so these are scalar loads).
-__device__ __forceinline__ const BatchJobDesc& job_of(const BatchTable* tab, const BatchClass& c,
-                                                      int t)
-{
-    int lo = c.job_begin, hi = c.job_begin + c.njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tab->jobs[mid].tile_begin <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    return tab->jobs[lo];
-}
-
-template <int R, int TY, typename T, bool GATE, int TXW>
+template <int R, int TY, typename T, bool GATE, int TXW, bool QUEUE>
 __global__ __launch_bounds__((M9Geo<R, TY, TXW>::THREADS))
-__attribute__((amdgpu_waves_per_eu(R <= 3 ? 3 : 2))) void mean9_multi(
-    const BatchTable* __restrict__ tab, int cls, uint32_t gate)
+__attribute__((amdgpu_waves_per_eu((m9_waves<R, M9Geo<R, TY, TXW>::THREADS>())))) void mean9_multi(
+    BatchTable* __restrict__ tab, int cls, uint32_t gate)
 {
     __shared__ __align__(16) M9SmemAny<R, TY, TXW, T> sm;
+    __shared__ int s_t;
     constexpr int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
-    const BatchClass c = tab->c[cls];
-    const int t = xcd_tile(blockIdx.x, c.total);
-    const BatchJobDesc d = job_of(tab, c, t);
-    const int local = t - d.tile_begin;
-    const int bx = local % d.tiles_x;
-    const int rest = local / d.tiles_x;
-    const int by = rest % d.tiles_y;
-    const int bz = rest / d.tiles_y;
-    const Geom g{d.nx, d.ny, d.nz};
-    const int z0 = bz * d.zs;
-    mean9_tile<R, TY, T, GATE, TXW>(sm, d.pairs != 0, static_cast<const T*>(d.in),
-                                    static_cast<T*>(d.out), g, bx * TXW, by * TY, z0,
-                                    min(z0 + d.zs, d.nz), gate, 1.0 / (9.0 * n));
+    for_class_tiles<TXW, TY, QUEUE>(tab, cls, &s_t, [&](const BatchJobDesc& d, int x0, int y0,
+                                                       int z0, int z1, int tid) {
+        mean9_tile<R, TY, T, GATE, TXW>(sm, d.pairs != 0, static_cast<const T*>(d.in),
+                                        static_cast<T*>(d.out), Geom{d.nx, d.ny, d.nz}, x0, y0,
+                                        z0, z1, gate, 1.0 / (9.0 * n), tid);
+    });
 }
 
-template <int R, typename T, bool GATE>
-__global__ __launch_bounds__(MV9Shape<R>::THREADS)
-__attribute__((amdgpu_waves_per_eu(MV9Shape<R>::WAVES))) void minvar9_multi(const BatchTable* __restrict__ tab, int cls,
-                                                     uint32_t gate)
+template <int R, typename T, bool GATE, bool WT, bool QUEUE>
+__global__ __launch_bounds__((MV9Shape<R, WT>::THREADS))
+__attribute__((amdgpu_waves_per_eu((MV9Shape<R, WT>::WAVES)))) void minvar9_multi(
+    BatchTable* __restrict__ tab, int cls, uint32_t gate)
 {
-    __shared__ __align__(16) MV9Smem<R, T> sm;
+    using S = MV9Shape<R, WT>;
+    __shared__ __align__(16) MV9Smem<R, T, WT> sm;
+    __shared__ int s_t;
     constexpr int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
-    const BatchClass c = tab->c[cls];
-    const int t = xcd_tile(blockIdx.x, c.total);
-    const BatchJobDesc d = job_of(tab, c, t);
-    const int local = t - d.tile_begin;
-    const int bx = local % d.tiles_x;
-    const int rest = local / d.tiles_x;
-    const int by = rest % d.tiles_y;
-    const int bz = rest / d.tiles_y;
-    const Geom g{d.nx, d.ny, d.nz};
-    const int z0 = bz * d.zs;
-    minvar9_tile<R, T, GATE>(sm, static_cast<const T*>(d.in), static_cast<T*>(d.out), g,
-                             bx * MV9Shape<R>::TX, by * MV9Shape<R>::TY, z0,
-                             min(z0 + d.zs, d.nz), gate, (double)n, 1.0 / n);
+    for_class_tiles<S::TX, S::TY, QUEUE>(tab, cls, &s_t, [&](const BatchJobDesc& d, int x0,
+                                                            int y0, int z0, int z1, int tid) {
+        minvar9_tile<R, T, GATE, WT>(sm, static_cast<const T*>(d.in), static_cast<T*>(d.out),
+                                     Geom{d.nx, d.ny, d.nz}, x0, y0, z0, z1, gate, (double)n,
+                                     1.0 / n, tid);
+    });
 }
 
-// A launchable class kernel: function, block size.
-struct ClassKernel {
-    const void* fn = nullptr;
-    int threads = 0;
-};
-
-template <int R, typename T, bool GATE, int TY, int TXW>
+template <int R, typename T, bool GATE, int TY, int TXW, bool QUEUE>
 ClassKernel mean9_kernel()
 {
-    return {reinterpret_cast<const void*>(mean9_multi<R, TY, T, GATE, TXW>),
+    return {reinterpret_cast<const void*>(mean9_multi<R, TY, T, GATE, TXW, QUEUE>),
             M9Geo<R, TY, TXW>::THREADS};
 }
 
+// Queue mode is compiled for the 64 x 16 tile only.
 template <int R, typename T, bool GATE>
-ClassKernel mean9_kernel_v(int variant)
+ClassKernel mean9_kernel_v(int variant, bool queue)
 {
+    if (queue) return mean9_kernel<R, T, GATE, 16, 64, true>();
     switch (variant) {
-    case 1: return mean9_kernel<R, T, GATE, 32, 64>();
-    case 2: return mean9_kernel<R, T, GATE, 16, 32>();
-    case 3: return mean9_kernel<R, T, GATE, 32, 32>();
-    default: return mean9_kernel<R, T, GATE, 16, 64>();  // variant 0: 64 x 16
+    case 1: return mean9_kernel<R, T, GATE, 32, 64, false>();
+    case 2: return mean9_kernel<R, T, GATE, 16, 32, false>();
+    case 3: return mean9_kernel<R, T, GATE, 32, 32, false>();
+    default: return mean9_kernel<R, T, GATE, 16, 64, false>();  // variant 0: 64 x 16
     }
 }
 
+template <int R, typename T, bool GATE, bool WT>
+ClassKernel minvar9_kernel(bool queue)
+{
+    if (queue)
+        return {reinterpret_cast<const void*>(minvar9_multi<R, T, GATE, WT, true>),
+                MV9Shape<R, WT>::THREADS};
+    return {reinterpret_cast<const void*>(minvar9_multi<R, T, GATE, WT, false>),
+            MV9Shape<R, WT>::THREADS};
+}
+
 template <int R, typename T>
-ClassKernel class_kernel_rt(int rule, bool gate, int variant)
+ClassKernel class_kernel_rt(int rule, bool gate, int variant, bool queue)
 {
     if (rule == LNF_MEAN9)
-        return gate ? mean9_kernel_v<R, T, true>(variant) : mean9_kernel_v<R, T, false>(variant);
-    if (gate) return {reinterpret_cast<const void*>(minvar9_multi<R, T, true>), MV9Shape<R>::THREADS};
-    return {reinterpret_cast<const void*>(minvar9_multi<R, T, false>), MV9Shape<R>::THREADS};
+        return gate ? mean9_kernel_v<R, T, true>(variant, queue)
+                    : mean9_kernel_v<R, T, false>(variant, queue);
+    if (variant == 1)
+        return gate ? minvar9_kernel<R, T, true, true>(queue) : minvar9_kernel<R, T, false, true>(queue);
+    return gate ? minvar9_kernel<R, T, true, false>(queue) : minvar9_kernel<R, T, false, false>(queue);
 }
 
 template <typename T>
-ClassKernel class_kernel_t(int rule, int r, bool gate, int variant)
+ClassKernel class_kernel_t(int rule, int r, bool gate, int variant, bool queue)
 {
     switch (r) {
-    case 1: return class_kernel_rt<1, T>(rule, gate, variant);
-    case 2: return class_kernel_rt<2, T>(rule, gate, variant);
-    case 3: return class_kernel_rt<3, T>(rule, gate, variant);
-    default: return class_kernel_rt<4, T>(rule, gate, variant);
+    case 1: return class_kernel_rt<1, T>(rule, gate, variant, queue);
+    case 2: return class_kernel_rt<2, T>(rule, gate, variant, queue);
+    case 3: return class_kernel_rt<3, T>(rule, gate, variant, queue);
+    default: return class_kernel_rt<4, T>(rule, gate, variant, queue);
     }
 }
 
 // Kernel of class c (= batch_class(r, dtype)) for a tile variant.
-ClassKernel class_kernel(int rule, int c, bool gate, int variant)
+ClassKernel class_kernel(int rule, int c, bool gate, int variant, bool queue)
 {
     const int r = c / 2 + 1;
-    return (c & 1) ? class_kernel_t<uint16_t>(rule, r, gate, variant)
-                   : class_kernel_t<uint8_t>(rule, r, gate, variant);
+    return (c & 1) ? class_kernel_t<uint16_t>(rule, r, gate, variant, queue)
+                   : class_kernel_t<uint8_t>(rule, r, gate, variant, queue);
 }
 
 struct BatchSlot {
@@ -185,6 +149,11 @@ struct BatchState {
     std::mutex mu;
     BatchSlot slot[kSlots];
     int next = 0;
+    // A call captured in a HIP graph keeps its table for the graph's lifetime:
+    // its replays copy that host table again.  Those slots are allocated with
+    // the rest (no allocation may happen during a capture) and never reused.
+    BatchSlot captured[kCaptureSlots];
+    int ncaptured = 0;
 };
 
 namespace {
@@ -214,11 +183,24 @@ int build_slot(BatchSlot& s)
 
 }  // namespace
 
+int batch_state_init(lnf_ctx* h)
+{
+    BatchState* st = new (std::nothrow) BatchState();
+    if (!st) return LNF_ENOMEM;
+    h->batch = st;
+    for (auto& s : st->slot)
+        if (int rc = build_slot(s)) return rc;
+    for (auto& s : st->captured)
+        if (int rc = build_slot(s)) return rc;
+    return LNF_OK;
+}
+
 void batch_state_free(lnf_ctx* h)
 {
     BatchState* st = h->batch;
     if (!st) return;
     for (auto& s : st->slot) free_slot(s);
+    for (auto& s : st->captured) free_slot(s);
     delete st;
     h->batch = nullptr;
 }
@@ -251,38 +233,26 @@ int validate_jobs(const lnf_ctx* h, const lnf_job* jobs, int n, std::vector<Geom
 }
 
 int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>& geoms,
-                 hipStream_t stream)
+                 hipStream_t stream, bool queue)
 {
-    if (h->geom) {  // geometry variants: the cluster-gather kernel, one launch per job
-        for (int i = 0; i < n; ++i) {
-            const TileCfg cfg = ctx_tile(h, h->rule, jobs[i].dtype, jobs[i].radius, geoms[i]);
-            if (launch_rule(h->rule, h->geom, jobs[i].in, jobs[i].out, jobs[i].dtype,
-                            jobs[i].radius, geoms[i], h->gate, cfg, stream) != hipSuccess)
-                return LNF_EHIP;
-        }
-        return LNF_OK;
-    }
-    {
-        std::lock_guard<std::mutex> lk(h->mu);
-        if (!h->batch) {
-            h->batch = new (std::nothrow) BatchState();
-            if (!h->batch) return LNF_ENOMEM;
-        }
-    }
     BatchState* st = h->batch;
+    if (!st) return LNF_ENOMEM;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return LNF_EHIP;
+    const bool capturing = cap != hipStreamCaptureStatusNone;
     std::lock_guard<std::mutex> lk(st->mu);
-    BatchSlot& s = st->slot[st->next];
-    st->next = (st->next + 1) % kSlots;
-    if (!s.host) {
-        const int rc = build_slot(s);
-        if (rc) {
-            free_slot(s);
-            return rc;
-        }
+    BatchSlot* sp;
+    if (capturing) {
+        if (st->ncaptured == kCaptureSlots) return LNF_EBUSY;
+        sp = &st->captured[st->ncaptured++];
+    } else {
+        sp = &st->slot[st->next];
+        st->next = (st->next + 1) % kSlots;
+        // the slot's previous table may still be read by its kernels
+        if (sp->pending && hipEventSynchronize(sp->done) != hipSuccess) return LNF_EHIP;
+        sp->pending = false;
     }
-    // the slot's previous table may still be read by its kernels
-    if (s.pending && hipEventSynchronize(s.done) != hipSuccess) return LNF_EHIP;
-    s.pending = false;
+    BatchSlot& s = *sp;
 
     // order: by class, then larger jobs first (their tiles get the low indices)
     std::vector<int> order(n);
@@ -297,28 +267,41 @@ int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>
     });
     BatchTable* tab = s.host;
     ClassKernel kern[kClasses];
+    GeomClassKernel gk[kClasses];
+    int grid[kClasses] = {};
     int k = 0;
     for (int c = 0; c < kClasses; ++c) {
         BatchClass& cl = tab->c[c];
-        cl = BatchClass{0, 0, k, 0};
+        cl = BatchClass{0, 0, k, 0, 0u, {0, 0, 0}};
         int kend = k;
         while (kend < n && batch_class(jobs[order[kend]].radius, jobs[order[kend]].dtype) == c)
             ++kend;
         if (kend == k) continue;
         const int r = c / 2 + 1, dtype = (c & 1) ? LNF_U16 : LNF_U8;
         // tile variant: the tuned one of the class's largest volume, else the
-        // default for (dtype, r)
+        // default for that volume
         int variant = 0, tx = 32, ty = 8;
-        if (h->rule == LNF_MEAN9) {
-            const TileCfg cfg = ctx_tile(h, h->rule, dtype, r, geoms[order[k]]);
-            variant = cfg.variant >= 0 && cfg.variant < mean9_variants()
-                          ? cfg.variant
-                          : mean9_default_variant(dtype, r);
-            mean9_tile_shape(variant, &tx, &ty);
+        const TileCfg cfg = ctx_tile(h, h->rule, dtype, r, geoms[order[k]]);
+        if (h->geom) {
+            gk[c] = geometry_class_kernel(h->rule, h->geom, dtype, r);
+            kern[c] = gk[c].k;
+            tx = gk[c].tx;
+            ty = gk[c].ty;
         } else {
-            minvar9_tile_shape(0, r, &tx, &ty);
+            if (h->rule == LNF_MEAN9) {
+                variant = queue ? 0
+                          : cfg.variant >= 0 && cfg.variant < mean9_variants()
+                              ? cfg.variant
+                              : mean9_default_variant(dtype, r);
+                mean9_tile_shape(variant, &tx, &ty);
+            } else {
+                variant = cfg.variant >= 0 && cfg.variant < minvar9_variants()
+                              ? cfg.variant
+                              : minvar9_default_variant(dtype, r, geoms[order[k]]);
+                minvar9_tile_shape(variant, r, &tx, &ty);
+            }
+            kern[c] = class_kernel(h->rule, c, h->gate != 0, variant, queue);
         }
-        kern[c] = class_kernel(h->rule, c, h->gate != 0, variant);
         // z-strips: the class's volumes differ in depth, so its workgroups
         // differ in length and the launch ends on a tail of the longest ones.
         // About 16 workgroups per resident slot keep that tail short (measured
@@ -352,6 +335,8 @@ int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>
         }
         cl.njobs = kend - k;
         cl.variant = variant;
+        // queue mode: one workgroup per resident slot, at most one per tile
+        grid[c] = queue ? (int)std::min<long long>(cl.total, target) : cl.total;
         k = kend;
     }
     const size_t used = offsetof(BatchTable, jobs) + (size_t)std::max(n, 1) * sizeof(BatchJobDesc);
@@ -359,16 +344,28 @@ int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>
         return LNF_EHIP;
     for (int c = 0; c < kClasses; ++c) {
         if (tab->c[c].total == 0) continue;
-        const BatchTable* dtab = s.dev;
+        BatchTable* dtab = s.dev;
         int cls = c;
         uint32_t gate = h->gate;
-        void* args[] = {&dtab, &cls, &gate};
-        if (hipLaunchKernel(kern[c].fn, dim3(tab->c[c].total), dim3(kern[c].threads), args, 0,
-                            stream) != hipSuccess)
-            return LNF_EHIP;
+        hipError_t e;
+        if (h->geom) {
+            const void* nul = nullptr;
+            void* nulo = nullptr;
+            Geom g0{0, 0, 0};
+            int z = 0, total = tab->c[c].total;
+            double dn = gk[c].dn, inv = gk[c].inv;
+            void* args[] = {&dtab, &cls, &nul, &nulo, &g0, &z, &z, &z, &total, &gate, &dn, &inv};
+            e = hipLaunchKernel(kern[c].fn, dim3(grid[c]), dim3(kern[c].threads), args, 0, stream);
+        } else {
+            void* args[] = {&dtab, &cls, &gate};
+            e = hipLaunchKernel(kern[c].fn, dim3(grid[c]), dim3(kern[c].threads), args, 0, stream);
+        }
+        if (e != hipSuccess) return LNF_EHIP;
     }
-    if (hipEventRecord(s.done, stream) != hipSuccess) return LNF_EHIP;
-    s.pending = true;
+    if (!capturing) {
+        if (hipEventRecord(s.done, stream) != hipSuccess) return LNF_EHIP;
+        s.pending = true;
+    }
     return LNF_OK;
 }
 
@@ -376,13 +373,21 @@ int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>
 
 using namespace lnf;
 
-extern "C" int lnf_filter_batch(lnf_handle h, const lnf_job* jobs, int n, hipStream_t stream)
+extern "C" int lnf_filter_batch_mode(lnf_handle h, const lnf_job* jobs, int n, hipStream_t stream,
+                                     int mode)
 {
-    if (!h) return LNF_EINVAL;
+    if (!h || (mode != LNF_BATCH_GRID && mode != LNF_BATCH_PERSISTENT)) return LNF_EINVAL;
+    // queue mode runs the default geometry only
+    if (mode == LNF_BATCH_PERSISTENT && h->geom) return LNF_EINVAL;
     std::vector<Geom> geoms;
     DeviceGuard dg(h->device);
     if (!dg.ok()) return LNF_EHIP;
     int rc = validate_jobs(h, jobs, n, &geoms);
     if (rc || n == 0) return rc;
-    return batch_launch(h, jobs, n, geoms, stream);
+    return batch_launch(h, jobs, n, geoms, stream, mode == LNF_BATCH_PERSISTENT);
+}
+
+extern "C" int lnf_filter_batch(lnf_handle h, const lnf_job* jobs, int n, hipStream_t stream)
+{
+    return lnf_filter_batch_mode(h, jobs, n, stream, LNF_BATCH_GRID);
 }

@@ -1,0 +1,107 @@
+// Job table of a batch launch (lnf_filter_batch): the volumes of each class of
+// equal (radius, voxel type), their tile grids, and the device-side walk from a
+// class tile index to a volume and its tile.  Shared by the batch kernels of
+// batch.hip and the geometry-variant kernels of cluster.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_common.h"
+#include "lnf.h"
+#include "lnf_internal.h"
+
+namespace lnf {
+
+struct BatchJobDesc {
+    const void* in;
+    void* out;
+    int nx, ny, nz;
+    int tiles_x, tiles_y, zs, tile_begin;  // tile_begin: first tile in its class
+    int pairs;                             // MEAN9 stages element pairs (mean9_pairs_ok)
+};
+
+struct BatchClass {
+    int total;       // tiles in this class
+    int njobs;       // jobs in this class
+    int job_begin;   // index of its first job in `jobs`
+    int variant;     // tile variant of the class
+    unsigned next;   // queue mode: next tile to hand out (uploaded as 0)
+    int pad[3];
+};
+
+constexpr int kClasses = 2 * LNF_RADIUS_MAX;  // (radius, voxel type)
+
+// A launchable class kernel: function, block size.
+struct ClassKernel {
+    const void* fn = nullptr;
+    int threads = 0;
+};
+
+// The kernel of a geometry-variant class (cluster.hip): launched with the
+// arguments (table, class, nullptr, nullptr, Geom{}, 0, 0, 0, total, gate, dn,
+// inv) over `total` workgroups; TX x TY output tiles.
+struct GeomClassKernel {
+    ClassKernel k;
+    int tx, ty;
+    double dn, inv;
+};
+GeomClassKernel geometry_class_kernel(int rule, uint32_t geom, int dtype, int r);
+
+// Class of a (radius, dtype) pair.
+constexpr int batch_class(int r, int dtype) { return 2 * (r - 1) + (dtype == LNF_U16 ? 1 : 0); }
+
+struct BatchTable {
+    BatchClass c[kClasses];
+    BatchJobDesc jobs[LNF_BATCH_MAX];
+};
+
+// Job of class tile t: the last job whose first tile is <= t (uniform per
+// workgroup, so these are scalar loads).
+__device__ __forceinline__ const BatchJobDesc& job_of(const BatchTable* tab, const BatchClass& c,
+                                                      int t)
+{
+    int lo = c.job_begin, hi = c.job_begin + c.njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab->jobs[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return tab->jobs[lo];
+}
+
+// Runs body(job, x0, y0, z0, z1, tid) on tiles of class `cls` with TX x TY
+// output tiles.  Grid mode: workgroup b takes class tile b (XCD-aware order).
+// Queue mode: each workgroup takes tiles from the class counter until none is
+// left (the grid is the resident workgroups, not the tiles), with tile_tid as
+// the thread index; s_t is one LDS word.
+template <int TX, int TY, bool QUEUE, typename F>
+__device__ __forceinline__ void for_class_tiles(BatchTable* tab, int cls, int* s_t, F&& body)
+{
+    const int total = tab->c[cls].total;
+    auto run = [&](int t, int tid) {
+        const BatchJobDesc d = job_of(tab, tab->c[cls], t);
+        const int local = t - d.tile_begin;
+        const int bx = local % d.tiles_x;
+        const int rest = local / d.tiles_x;
+        const int by = rest % d.tiles_y;
+        const int bz = rest / d.tiles_y;
+        const int z0 = bz * d.zs;
+        body(d, bx * TX, by * TY, z0, min(z0 + d.zs, d.nz), tid);
+    };
+    if constexpr (!QUEUE) {
+        run(xcd_tile(blockIdx.x, total), (int)threadIdx.x);
+    } else {
+        for (;;) {
+            if (threadIdx.x == 0) *s_t = (int)atomicAdd(&tab->c[cls].next, 1u);
+            __syncthreads();
+            const int t = *s_t;
+            __syncthreads();  // every thread has read s_t before it is written again
+            if (t >= total) break;
+            run(t, tile_tid());
+        }
+    }
+}
+
+}  // namespace lnf

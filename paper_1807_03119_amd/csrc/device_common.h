@@ -19,6 +19,18 @@ __device__ __forceinline__ int xcd_tile(int b, int total)
     return xcd * q + min(xcd, rem) + idx;
 }
 
+// The thread index for a tile of a loop that runs several tiles per
+// workgroup: through an empty asm, so that the values a tile derives from it
+// are computed per tile instead of being hoisted out of the loop, where they
+// would stay live (and spill) across all of it.  Kernels that run one tile
+// pass threadIdx.x itself.
+__device__ __forceinline__ int tile_tid()
+{
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    return tid;
+}
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 // ---- buffer resources -------------------------------------------------------

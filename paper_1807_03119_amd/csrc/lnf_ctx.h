@@ -59,6 +59,7 @@ hipError_t launch_rule(int rule, uint32_t geom, const void* in, void* out, int d
 
 // Batch path (batch.hip).
 int validate_jobs(const lnf_ctx* h, const lnf_job* jobs, int n, std::vector<Geom>* geoms);
+int batch_state_init(lnf_ctx* h);  // the job-table slots (freed by batch_state_free)
 void batch_state_free(lnf_ctx* h);
 void otsu_scratch_free(lnf_ctx* h);
 void entropy_scratch_free(lnf_ctx* h);

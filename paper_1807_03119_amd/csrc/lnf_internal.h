@@ -52,6 +52,8 @@ hipError_t launch_window(int kind, const void* in, void* out, int dtype, int r, 
 
 // ---- MINVAR9 (least-variance cluster) -------------------------------------
 int minvar9_variants();
+// Default tile variant for a volume of plane g.nx x g.ny.
+int minvar9_default_variant(int dtype, int r, Geom g);
 void minvar9_tile_shape(int variant, int r, int* tx, int* ty);  // output tile of (variant, r)
 hipError_t launch_minvar9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
                           TileCfg cfg, hipStream_t s, TileCfg* plan = nullptr);

@@ -20,18 +20,10 @@
 namespace lnf {
 namespace {
 
-// Waves per SIMD the tile kernels are compiled for: three up to r = 3 (the
-// tile body fits 168 VGPRs there), two at r = 4.
-template <int R>
-constexpr int m9_waves()
-{
-    return R <= 3 ? 3 : 2;
-}
-
 // Single-volume wrapper around the streaming tile body of mean9_tile.h.
 template <int R, int TY, typename T, bool GATE, int TXW>
 __global__ __launch_bounds__((M9Geo<R, TY, TXW>::THREADS))
-__attribute__((amdgpu_waves_per_eu(m9_waves<R>()))) void mean9_stream(
+__attribute__((amdgpu_waves_per_eu((m9_waves<R, M9Geo<R, TY, TXW>::THREADS>())))) void mean9_stream(
     const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
     int total, uint32_t gate, double inv9n, int pairs)
 {
@@ -43,14 +35,14 @@ __attribute__((amdgpu_waves_per_eu(m9_waves<R>()))) void mean9_stream(
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
     mean9_tile<R, TY, T, GATE, TXW>(sm, pairs != 0, in, out, g, bx * TXW, by * TY, z0,
-                                    min(z0 + zs, g.nz), gate, inv9n);
+                                    min(z0 + zs, g.nz), gate, inv9n, (int)threadIdx.x);
 }
 
 // The paper's mean filter (eq. 4): the box term of the same streaming tile,
 // 64 x 16 tiles.
 template <int R, typename T, bool GATE>
 __global__ __launch_bounds__((M9Geo<R, 16, 64>::THREADS))
-__attribute__((amdgpu_waves_per_eu(m9_waves<R>()))) void box_mean_stream(
+__attribute__((amdgpu_waves_per_eu((m9_waves<R, M9Geo<R, 16, 64>::THREADS>())))) void box_mean_stream(
     const T* __restrict__ in, T* __restrict__ out, Geom g, int zs, int tiles_x, int tiles_y,
     int total, uint32_t gate, double invn, int pairs)
 {
@@ -62,7 +54,7 @@ __attribute__((amdgpu_waves_per_eu(m9_waves<R>()))) void box_mean_stream(
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
     mean9_tile<R, 16, T, GATE, 64, true>(sm, pairs != 0, in, out, g, bx * 64, by * 16, z0,
-                                         min(z0 + zs, g.nz), gate, invn);
+                                         min(z0 + zs, g.nz), gate, invn, (int)threadIdx.x);
 }
 
 template <int R, typename T, bool GATE>

@@ -98,6 +98,15 @@ struct M9Geo {
 // LDS one workgroup may use: three 256-thread workgroups per CU (160 KiB).
 constexpr int kM9LdsBudget = 53 * 1024;
 
+// Waves per SIMD the tile kernels are compiled for: three up to r = 3 (the
+// tile body fits 168 VGPRs there), two at r = 4 and for 512-thread
+// workgroups (one of those per CU holds two waves per SIMD).
+template <int R, int THREADS>
+constexpr int m9_waves()
+{
+    return (R <= 3 && THREADS <= 256) ? 3 : 2;
+}
+
 template <int R, int TY, int TXW, bool PK, int MODE>
 struct M9Shape : M9Geo<R, TY, TXW, PK> {
     using G = M9Geo<R, TY, TXW, PK>;
@@ -147,7 +156,7 @@ template <int R, int TY, typename T, bool GATE, int TXW, bool PK, int MODE>
 __device__ __forceinline__ bool mean9_tile_body(M9Smem<R, TY, TXW, PK, MODE>& sm,
                                                 const T* __restrict__ in, T* __restrict__ out,
                                                 Geom g, int x0, int y0, int z0, int z1,
-                                                uint32_t gate, double inv_div)
+                                                uint32_t gate, double inv_div, int tid)
 {
     using S = M9Shape<R, TY, TXW, PK, MODE>;
     constexpr bool kBox = MODE == kM9Box, kPQ = MODE == kM9Packed;
@@ -156,7 +165,6 @@ __device__ __forceinline__ bool mean9_tile_body(M9Smem<R, TY, TXW, PK, MODE>& sm
     constexpr int EPW = S::EPW, NRB = S::NRB, PF = S::PF;
     // output slice of iteration k: z0 + k - 1 - LAG
     constexpr int LAG = kBox ? 3 * R : 4 * R;
-    const int tid = threadIdx.x;
     // wave index as a scalar, so the LDS DMA destinations are scalar arithmetic
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const size_t plane = (size_t)g.nx * g.ny;
@@ -420,28 +428,29 @@ union M9SmemAny {
 // One tile; `pairs` (mean9_pairs_ok for the volume) selects paired staging
 // for the tiles whose x halo stays inside the volume.  MEAN9 runs packed and,
 // where that can stop, again unpacked for a tile whose packed run stopped.
+// tid: threadIdx.x (see tile_tid for loops over several tiles).
 template <int R, int TY, typename T, bool GATE, int TXW = 64, bool BOX = false>
 __device__ __forceinline__ void mean9_tile(M9SmemAny<R, TY, TXW, T, BOX>& sm, bool pairs,
                                            const T* __restrict__ in, T* __restrict__ out, Geom g,
                                            int x0, int y0, int z0, int z1, uint32_t gate,
-                                           double inv_div)
+                                           double inv_div, int tid)
 {
     constexpr int H = 2 * R, LXE = TXW + 4 * R;
     constexpr int kMode = BOX ? kM9Box : kM9Packed;
     if (pairs && x0 - H >= 0 && x0 - H + LXE <= g.nx) {
         if (mean9_tile_body<R, TY, T, GATE, TXW, true, kMode>(sm.p, in, out, g, x0, y0, z0, z1,
-                                                              gate, inv_div))
+                                                              gate, inv_div, tid))
             return;
         if constexpr (m9_needs_exact<T, R, BOX>())
             mean9_tile_body<R, TY, T, GATE, TXW, true, kM9Exact>(sm.px, in, out, g, x0, y0, z0, z1,
-                                                                 gate, inv_div);
+                                                                 gate, inv_div, tid);
     } else {
         if (mean9_tile_body<R, TY, T, GATE, TXW, false, kMode>(sm.e, in, out, g, x0, y0, z0, z1,
-                                                               gate, inv_div))
+                                                               gate, inv_div, tid))
             return;
         if constexpr (m9_needs_exact<T, R, BOX>())
             mean9_tile_body<R, TY, T, GATE, TXW, false, kM9Exact>(sm.ex, in, out, g, x0, y0, z0,
-                                                                  z1, gate, inv_div);
+                                                                  z1, gate, inv_div, tid);
     }
 }
 

@@ -22,7 +22,7 @@ __attribute__((amdgpu_waves_per_eu(MV9Shape<R, WT>::WAVES))) void minvar9_planes
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
     minvar9_tile<R, T, GATE, WT>(sm, in, out, g, bx * S::TX, by * S::TY, z0, min(z0 + zs, g.nz),
-                                 gate, dn, invn);
+                                 gate, dn, invn, (int)threadIdx.x);
 }
 
 template <int R, typename T, bool WT>
@@ -64,11 +64,8 @@ template <typename T>
 hipError_t dispatch_r(const void* in, void* out, int r, Geom g, uint32_t gate, TileCfg cfg,
                       hipStream_t s, TileCfg* plan)
 {
-    // default variant: the wide tile on large planes where it measured faster
-    // (uint16 up to r = 3, uint8 at r = 3), else 32 x 16
-    int v = cfg.variant;
-    if (v < 0)
-        v = (g.nx >= 256 && g.ny >= 256 && r <= 3 && (sizeof(T) == 2 || r == 3)) ? 1 : 0;
+    const int v = cfg.variant >= 0 ? cfg.variant
+                                   : minvar9_default_variant(sizeof(T) == 1 ? LNF_U8 : LNF_U16, r, g);
     if (plan) plan->variant = v;
     switch (r) {
     case 1: return launch_variant<1, T>(v, in, out, g, gate, cfg.zs, s, plan);
@@ -84,6 +81,13 @@ hipError_t dispatch_r(const void* in, void* out, int r, Geom g, uint32_t gate, T
 // 0: 32 x 16 outputs, 256 threads; 1: 64 x 16 outputs, 512 threads (up to
 // r = 3; the same tile as 0 at r = 4)
 int minvar9_variants() { return 2; }
+
+// The wide tile on large planes where it measured faster (uint16 up to r = 3,
+// uint8 at r = 3), else 32 x 16.
+int minvar9_default_variant(int dtype, int r, Geom g)
+{
+    return (g.nx >= 256 && g.ny >= 256 && r <= 3 && (dtype == LNF_U16 || r == 3)) ? 1 : 0;
+}
 
 void minvar9_tile_shape(int variant, int r, int* tx, int* ty)
 {

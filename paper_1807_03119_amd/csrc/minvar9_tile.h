@@ -17,10 +17,11 @@ using MV9Smem = PTSmem<R, R, kClusterBox, kRuleMinVar9, T, WT>;
 template <int R, typename T, bool GATE, bool WT = false>
 __device__ __forceinline__ void minvar9_tile(MV9Smem<R, T, WT>& sm, const T* __restrict__ in,
                                              T* __restrict__ out, Geom g, int x0, int y0, int z0,
-                                             int z1, uint32_t gate, double dn, double invn)
+                                             int z1, uint32_t gate, double dn, double invn,
+                                             int tid)
 {
     plane_tile<R, R, kClusterBox, kRuleMinVar9, T, GATE, WT>(sm, in, out, g, x0, y0, z0, z1, gate,
-                                                             dn, invn);
+                                                             dn, invn, tid);
 }
 
 }  // namespace lnf

@@ -175,12 +175,13 @@ struct PTSmem {
     uint32_t vo[PACK ? 4 : a16(S::GY * S::VP, 4)];  // MINVAR9: rounded means; MEAN9: B
 };
 
-// dn = n; inv = 1/n (MINVAR9) or 1/(9n) (MEAN9).
+// dn = n; inv = 1/n (MINVAR9) or 1/(9n) (MEAN9); tid: threadIdx.x (see
+// tile_tid for loops over several tiles).
 template <int R, int D, int SHAPE, int RULE, typename T, bool GATE, bool WT = false>
 __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
                                            const T* __restrict__ in, T* __restrict__ out, Geom g,
                                            int x0, int y0, int z0, int z1, uint32_t gate,
-                                           double dn, double inv)
+                                           double dn, double inv, int tid)
 {
     using S = PTShape<R, D, SHAPE, RULE, WT>;
     using SM = PTSmem<R, D, SHAPE, RULE, T, WT>;
@@ -193,7 +194,6 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
                   "16-byte LDS accesses need 16-byte aligned arrays");
     constexpr int kT = S::THREADS, LX = S::LX, GX = S::GX, XS = S::XS, YS = S::YS;
     constexpr int U = S::U, OPT = S::OPT, VP = S::VP;
-    const int tid = threadIdx.x;
     const size_t plane = (size_t)g.nx * g.ny;
     const uint32_t pbytes = (uint32_t)(plane * sizeof(T));
 

@@ -1,5 +1,6 @@
-"""Batch path (one graph launch over many volumes) and the autotuner: every
-output byte-identical to the oracle and to single-volume calls."""
+"""Batch path (one launch per (radius, dtype) group over many volumes, as a
+per-tile grid or a persistent tile queue) and the autotuner: every output
+byte-identical to the oracle and to single-volume calls."""
 import os
 import tempfile
 
@@ -50,12 +51,13 @@ def test_batch_small_mixed_vs_oracle(rule, gate):
 
 
 @pytest.mark.parametrize("rule", ["mean9", "minvar9"])
-def test_batch_full_mixed_workload_equals_single_calls(rule):
+@pytest.mark.parametrize("mode", [_lib.LNF_BATCH_GRID, _lib.LNF_BATCH_PERSISTENT])
+def test_batch_full_mixed_workload_equals_single_calls(rule, mode):
     """The 64-volume mixed batch (axes 64..384, uint8/uint16, r in 1..3)."""
     jobs = ph.batch_jobs()
     vols = [ph.batch_volume(j, device="cuda") for j in jobs]
     with _filter(rule) as f:
-        outs = f.batch([(v, j.radius) for v, j in zip(vols, jobs)])
+        outs = f.batch([(v, j.radius) for v, j in zip(vols, jobs)], mode=mode)
         singles = [f(v, j.radius) for v, j in zip(vols, jobs)]
         torch.cuda.synchronize()
         rng = np.random.default_rng(11)
@@ -143,3 +145,101 @@ def test_batch_extreme_values_both_types():
         outs = f.batch([(torch.from_numpy(v).cuda(), r) for v, r in jobs])
         for (v, r), o in zip(jobs, outs):
             np.testing.assert_array_equal(o.cpu().numpy(), oracle.filter_volume(v, r))
+
+
+@pytest.mark.parametrize("rule", ["mean9", "minvar9"])
+@pytest.mark.parametrize("gate", [0, 900])
+def test_batch_persistent_queue_small_and_repeated(rule, gate):
+    """The tile queue hands out every tile exactly once, also when there are
+    fewer tiles than resident workgroups, and the counters start at zero on
+    every call (the table upload clears them)."""
+    with _filter(rule, gate) as f:
+        for rep in range(3):
+            jobs = _small_jobs(300 + rep + gate, n=9)
+            outs = f.batch([(torch.from_numpy(v).cuda(), r) for v, r in jobs],
+                           mode=_lib.LNF_BATCH_PERSISTENT)
+            for (vol, r), out in zip(jobs, outs):
+                want = oracle.filter_volume(vol, r, RULES[rule][1], gate=gate)
+                np.testing.assert_array_equal(out.cpu().numpy(), want, err_msg=f"{vol.shape} r={r}")
+
+
+@pytest.mark.parametrize("geom", [_lib.LNF_GEOM_CROSS, _lib.LNF_GEOM_OFFSET_1,
+                                  _lib.LNF_GEOM_OFFSET_2R1,
+                                  _lib.LNF_GEOM_CROSS | _lib.LNF_GEOM_OFFSET_1])
+@pytest.mark.parametrize("rule", ["mean9", "minvar9"])
+def test_batch_geometry_variants_one_grid_per_group(geom, rule):
+    """Geometry-variant contexts batch their jobs by group like the default
+    geometry: the same bytes as single calls and as the oracle."""
+    from paper_1807_03119_amd.api import Filter
+    shape = oracle.CROSS if geom & _lib.LNF_GEOM_CROSS else oracle.BOX
+    offset = (oracle.OFFSET_ONE if geom & _lib.LNF_GEOM_OFFSET_1 else
+              oracle.OFFSET_TILE if geom & _lib.LNF_GEOM_OFFSET_2R1 else oracle.OFFSET_R)
+    jobs = _small_jobs(400 + geom, n=8)
+    with Filter(RULES[rule][0], 0, geometry=geom) as f:
+        devs = [torch.from_numpy(v).cuda() for v, _ in jobs]
+        outs = f.batch([(d, r) for d, (_, r) in zip(devs, jobs)])
+        for d, (vol, r), out in zip(devs, jobs, outs):
+            got = out.cpu().numpy()
+            np.testing.assert_array_equal(got, f(d, r).cpu().numpy())
+            want = oracle.filter_volume(vol, r, RULES[rule][1], shape=shape, offset=offset)
+            np.testing.assert_array_equal(got, want, err_msg=f"{vol.shape} r={r}")
+        assert _lib.lnf_filter_batch(f.handle, [(devs[0], torch.empty_like(devs[0]), 1)],
+                                     mode=_lib.LNF_BATCH_PERSISTENT) == _lib.LNF_EINVAL
+
+
+def test_batch_minvar9_wide_tile_groups():
+    """MINVAR9 groups of large planes take the wide tile (the single-volume
+    default there); same bytes as single calls."""
+    vols = [ph.ct_u12((300, 280, 24), seed=2500 + i) for i in range(2)]
+    vols.append(ph.random_volume((260, 256, 20), np.uint8, seed=2600))
+    with _filter("minvar9") as f:
+        devs = [torch.from_numpy(v).cuda() for v in vols]
+        for r in (1, 3):
+            outs = f.batch([(d, r) for d in devs])
+            for d, v, o in zip(devs, vols, outs):
+                np.testing.assert_array_equal(o.cpu().numpy(), f(d, r).cpu().numpy())
+            np.testing.assert_array_equal(outs[0].cpu().numpy(),
+                                          oracle.filter_volume(vols[0], r, oracle.MINVAR9))
+
+
+def test_batch_call_captured_in_a_graph_replays_exactly():
+    """A batch call (grid and queue mode) captured in a HIP graph: every replay,
+    with eager batch calls and synchronisations between the replays, gives the
+    eager bytes; the queue counters start at zero on every replay.  Captures
+    beyond the reserved table slots are refused with LNF_EBUSY."""
+    jobs = _small_jobs(700, n=9)
+    other = _small_jobs(701, n=4)
+    with _filter("mean9") as f:
+        devs = [torch.from_numpy(v).cuda() for v, _ in jobs]
+        want = [f(d, r).cpu().numpy() for d, (_, r) in zip(devs, jobs)]
+        outs = [torch.empty_like(d) for d in devs]
+        triples = [(d, o, r) for d, o, (_, r) in zip(devs, outs, jobs)]
+        graphs = []
+        for mode in (_lib.LNF_BATCH_GRID, _lib.LNF_BATCH_PERSISTENT):
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                rc = _lib.lnf_filter_batch(f.handle, triples, mode=mode)
+            assert rc == _lib.LNF_OK
+            graphs.append(g)
+            for rep in range(3):
+                for o in outs:
+                    o.zero_()
+                torch.cuda.synchronize()
+                g.replay()
+                torch.cuda.synchronize()
+                for o, w, (v, r) in zip(outs, want, jobs):
+                    np.testing.assert_array_equal(o.cpu().numpy(), w, err_msg=f"mode {mode} rep {rep} r={r}")
+                # eager work between replays, on the same context
+                eo = f.batch([(torch.from_numpy(v).cuda(), r) for v, r in other])
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(eo[0].cpu().numpy(), oracle.filter_volume(*other[0]))
+        # two more captures fit the four reserved slots; the fifth is refused
+        codes = []
+        for _ in range(3):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                codes.append(_lib.lnf_filter_batch(f.handle, triples))
+            graphs.append(g)
+        assert codes == [_lib.LNF_OK, _lib.LNF_OK, _lib.LNF_EBUSY]
+        del graphs
