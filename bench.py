@@ -171,6 +171,38 @@ def batch_benchmark(rule_code, stream, steps=5):
     return res
 
 
+def surface_benchmark(vol, radius, threshold, stream):
+    """First-hit pass (z-rays, both directions) at Otsu's threshold and the
+    surface pipeline (first hit, then both rules at the hits) on the benchmark
+    volume.  Algorithmic bytes of the first-hit pass: every ray reads its
+    column up to and including its hit (the whole column for a miss) and
+    writes 12 bytes."""
+    import torch
+    from paper_1807_03119_amd import _lib
+    from paper_1807_03119_amd.api import Filter
+    nz, ny, nx = vol.shape
+    esize = vol.element_size()
+    out = {"threshold": int(threshold), "rays": nx * ny}
+    g = Filter(_lib.LNF_MEAN9, 0)
+    for direction, name in ((1, "front"), (-1, "back")):
+        hits = g.first_hit(vol, threshold, direction)
+        z = hits[:, 2].to(torch.int64)
+        depth = torch.where(z < 0, torch.full_like(z, nz), z + 1 if direction == 1 else nz - z)
+        alg = int(depth.sum().item()) * esize + 12 * nx * ny
+        ms, _ = time_launches(lambda: g.first_hit(vol, threshold, direction), 20, 3, stream)
+        out[f"first_hit_{name}"] = {"ms": ms, "alg_bytes": alg, "GBps": alg / (ms * 1e-3) / 1e9,
+                                    "frac_of_hbm": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                    "hit_rays": int((z >= 0).sum().item()),
+                                    "mean_depth": float(depth.double().mean().item())}
+    g.close()
+    for rule_name, rc in (("mean9", _lib.LNF_MEAN9), ("minvar9", _lib.LNF_MINVAR9)):
+        g = Filter(rc, 0)
+        ms, _ = time_launches(lambda: g.surface(vol, radius, threshold, 1), 10, 2, stream)
+        out[f"pipeline_{rule_name}_r{radius}_ms"] = ms
+        g.close()
+    return out
+
+
 def serve_benchmark(rule_code, seconds, rate=300.0, pool_n=8, side=512):
     """Open-loop Poisson replay of the serving trace against the server, once
     with continuous batching and once with one lnf_filter per request in FIFO
@@ -244,22 +276,29 @@ def serve_benchmark(rule_code, seconds, rate=300.0, pool_n=8, side=512):
     return out
 
 
-def serve_sweep(rule_code, rates=(300, 1000, 3000, 10000, 20000), seconds=1.5, n_vols=24,
-                max_requests=20000):
+SWEEPS = {
+    # cube sides log-uniform in [lo, hi]; request rates (per second)
+    "large": (128, 512, (300, 1000, 3000, 10000, 20000)),
+    "small": (48, 160, (1000, 10000, 30000, 60000, 100000)),
+}
+
+
+def serve_sweep(rule_code, regime="large", seconds=1.5, n_vols=24, max_requests=20000):
     """Open-loop Poisson re-filter requests on device-resident volumes (no
-    upload in the loop): cube sides log-uniform 128..512, r in 1..3, at each
-    rate, served with continuous batching and with one launch per request in
-    FIFO order.  Reports p50/p99 latency (from the scheduled arrival) and the
-    served rate; the load where batching starts to win is where FIFO's queue
-    grows."""
+    upload in the loop): cube sides log-uniform in the regime's range, r in
+    1..3, at each of its rates, served with continuous batching and with one
+    launch per request in FIFO order.  Reports p50/p99 latency (from the
+    scheduled arrival) and the served rate per rate, and the rates at which
+    batching has the lower p99."""
     import math
 
     import numpy as np
     import torch
     from paper_1807_03119_amd import _lib, phantom
     from paper_1807_03119_amd.api import Filter, Server
+    lo, hi, rates = SWEEPS[regime]
     rng = np.random.default_rng(5700)
-    sides = [int(round(math.exp(rng.uniform(math.log(128), math.log(512))))) for _ in range(n_vols)]
+    sides = [int(round(math.exp(rng.uniform(math.log(lo), math.log(hi))))) for _ in range(n_vols)]
     hosts = []
     for i, sd in enumerate(sides):
         v = phantom.ct_u12((sd, sd, sd), seed=5800 + i, device="cuda")
@@ -268,7 +307,8 @@ def serve_sweep(rule_code, rates=(300, 1000, 3000, 10000, 20000), seconds=1.5, n
         hosts.append(hbuf)
         del v
     torch.cuda.synchronize()
-    out = {"volumes": n_vols, "voxels_per_volume_mean": float(np.mean([sd ** 3 for sd in sides])),
+    out = {"side_range": [lo, hi], "volumes": n_vols,
+           "voxels_per_volume_mean": float(np.mean([sd ** 3 for sd in sides])),
            "seconds_per_rate": seconds, "rates": {}}
     for rate in rates:
         n = min(max_requests, int(rate * seconds))
@@ -304,8 +344,12 @@ def serve_sweep(rule_code, rates=(300, 1000, 3000, 10000, 20000), seconds=1.5, n
             srv.close()
             f.close()
         out["rates"][str(rate)] = row
-        log(f"  sweep {rate}/s: batched p99 {row['batched']['p99_ms']:.2f} ms, "
-            f"fifo p99 {row['fifo']['p99_ms']:.2f} ms")
+        log(f"  sweep {regime} {rate}/s: batched p50/p99 {row['batched']['p50_ms']:.2f}/"
+            f"{row['batched']['p99_ms']:.2f} ms {row['batched']['served_Gvox_s']:.1f} Gvox/s, "
+            f"fifo {row['fifo']['p50_ms']:.2f}/{row['fifo']['p99_ms']:.2f} ms "
+            f"{row['fifo']['served_Gvox_s']:.1f} Gvox/s")
+    out["batched_p99_lower_at"] = [int(k) for k, v in out["rates"].items()
+                                   if v["batched"]["p99_ms"] < v["fifo"]["p99_ms"]]
     return out
 
 
@@ -550,6 +594,7 @@ def main():
             extras["points"][f"{rule_name}_r{args.radius}_ms"] = ms2
             extras["points"][f"{rule_name}_r{args.radius}_Mpoints_s"] = npts / (ms2 * 1e-3) / 1e6
             g.close()
+        extras["surface"] = surface_benchmark(vol, args.radius, t_otsu, stream)
         log("timing the 64-volume mixed batch, both rules")
         extras["batch64"] = {name: batch_benchmark(rc, stream)
                              for name, rc in (("mean9", _lib.LNF_MEAN9), ("minvar9", _lib.LNF_MINVAR9))}
@@ -560,7 +605,7 @@ def main():
             log("serving burst of small re-filter requests")
             res["served"]["burst"] = burst_benchmark(rule_code)
             log("serving rate sweep on resident volumes")
-            res["served"]["sweep"] = serve_sweep(rule_code)
+            res["served"]["sweep"] = {k: serve_sweep(rule_code, k) for k in SWEEPS}
     if not args.no_cpu_baseline:
         f(vol, args.radius, out=out)
         torch.cuda.synchronize()

@@ -297,6 +297,33 @@ LNF_API int lnf_filter_points(lnf_handle h, const void* vol, const int64_t dims[
                               int radius, const int32_t* xyz, int64_t n, uint32_t* out,
                               hipStream_t stream);
 
+/*
+ * First-hit pass: the point list of the paper's surface intersection points
+ * (Section "Our Method") for rays parallel to z.  The ray through pixel
+ * (x, y) travels towards +z from slice 0 (direction 1) or towards -z from
+ * slice nz-1 (direction -1); its hit is the first voxel it meets whose value
+ * is >= threshold (the surface level, e.g. Otsu's T from lnf_histogram and
+ * lnf_otsu_threshold).  xyz: device int32 [ny*nx][3], written in full: entry
+ * y*nx + x receives (x, y, z_hit), z_hit = -1 when no voxel of the column
+ * reaches the threshold (lnf_filter_points reports 0xFFFFFFFF for such an
+ * entry).  Context rule, gate and geometry are not used.  Asynchronous on
+ * `stream`.  Errors: LNF_EINVAL (nulls, dtype, dims, direction not 1 or -1),
+ * LNF_EDEVICE, LNF_EHIP.
+ */
+LNF_API int lnf_first_hit(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                          uint32_t threshold, int direction, int32_t* xyz, hipStream_t stream);
+
+/*
+ * Surface pipeline: lnf_first_hit into xyz, then lnf_filter_points at those
+ * nx*ny points into out (device uint32 [ny*nx]): the context's filter at
+ * each ray's hit, 0xFFFFFFFF for a ray that meets nothing.  Both launches are
+ * asynchronous on `stream`.  Errors: as the two calls (a context with a
+ * non-default cluster geometry: LNF_EINVAL).
+ */
+LNF_API int lnf_filter_surface(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                               int radius, uint32_t threshold, int direction, int32_t* xyz,
+                               uint32_t* out, hipStream_t stream);
+
 /* ---- serving ------------------------------------------------------------ */
 /*
  * A request server with continuous batching.  Volumes are uploaded once and
@@ -305,10 +332,17 @@ LNF_API int lnf_filter_points(lnf_handle h, const void* vol, const int64_t dims[
  * (the server holds at most cap_bytes of device memory, allocated in chunks as
  * needed and kept until lnf_server_destroy; volumes and request outputs take
  * ranges of it, so evictions never free device memory), grouped
- * into micro-batches of everything admitted so far, and launched through the
- * batch path on a pool of streams, so batches issued while others run overlap
- * on the device.  Idle volumes are evicted least-recently-used first when the
- * cap is reached.  A worker thread owned by the server does the scheduling and
+ * into micro-batches in arrival order, and launched through the batch path on
+ * a pool of streams, so batches issued while others run overlap on the
+ * device.  A micro-batch takes requests until it holds max_batch of them or
+ * the next would take its voxels past the voxel budget (a request larger than
+ * the budget runs alone: it fills the device by itself).  A new micro-batch
+ * is launched while fewer than two are in flight or the voxels in flight stay
+ * under twice the budget; everything else waits in the queue, where later
+ * arrivals join it, so the device queue stays short and requests complete
+ * close to arrival order.  The FIFO mode follows the same bound with one
+ * request per launch.  Idle volumes are evicted least-recently-used first
+ * when the cap is reached.  A worker thread owned by the server does the scheduling and
  * completion polling; every function below is thread-safe.
  * Latency of a request = completion observed by the worker - its arrival time
  * (the client's scheduled arrival, so queueing delay is never hidden).
@@ -326,7 +360,8 @@ typedef struct {
     int32_t max_batch;        /* most requests per micro-batch (1..LNF_BATCH_MAX) */
     int32_t fail_batch;       /* test hook: the n-th batch (1-based) fails on the host
                                  before launch and its requests end LNF_ECANCELED; 0 = off */
-    int32_t reserved;
+    int32_t batch_mvox;       /* voxel budget of a micro-batch, in units of 2^20 voxels
+                                 (0: 32, i.e. 2^25 voxels); >= 0 */
 } lnf_server_options;
 
 typedef struct {
@@ -343,7 +378,8 @@ typedef struct {
 LNF_API int64_t lnf_server_now_ns(void);
 
 /* Create a server over context h (its rule and gate apply).  opt NULL: batched,
- * 200 GB cap, 4 streams, max_batch 256.  Errors: LNF_EINVAL, LNF_EHIP, LNF_ENOMEM. */
+ * 200 GB cap, 4 streams, max_batch 256, batch budget 2^25 voxels.
+ * Errors: LNF_EINVAL, LNF_EHIP, LNF_ENOMEM. */
 LNF_API int lnf_server_create(lnf_handle h, const lnf_server_options* opt, lnf_server_handle* srv);
 
 /* Finish all admitted work, fail still-pending requests with LNF_ECANCELED, free

@@ -64,7 +64,7 @@ LNF_SERVE_FIFO = 1
 class lnf_server_options(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("mode", ctypes.c_int32), ("cap_bytes", ctypes.c_uint64),
                 ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("fail_batch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fail_batch", ctypes.c_int32), ("batch_mvox", ctypes.c_int32)]
 
 
 class lnf_server_stats_t(ctypes.Structure):
@@ -100,6 +100,10 @@ def _declare(lib):
         "lnf_filter_points": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, _vp,
                               ctypes.c_int64, _vp, _vp],
         "lnf_otsu_threshold": [_vp, _i32, ctypes.POINTER(ctypes.c_uint32)],
+        "lnf_first_hit": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, ctypes.c_uint32, _i32,
+                          _vp, _vp],
+        "lnf_filter_surface": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32,
+                               ctypes.c_uint32, _i32, _vp, _vp, _vp],
         "lnf_filter_otsu": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, _vp, _vp,
                             ctypes.POINTER(ctypes.c_uint32)],
         "lnf_filter_mean": [_vp, _vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, _vp, _vp],
@@ -305,9 +309,9 @@ def lnf_server_now_ns() -> int:
 
 
 def lnf_server_create(h, mode=LNF_SERVE_BATCHED, cap_bytes=200 << 30, n_streams=4, max_batch=256,
-                      fail_batch=0):
+                      fail_batch=0, batch_mvox=0):
     opt = lnf_server_options(ctypes.sizeof(lnf_server_options), mode, cap_bytes, n_streams,
-                             max_batch, fail_batch, 0)
+                             max_batch, fail_batch, batch_mvox)
     srv = _vp()
     _check(lib().lnf_server_create(h, ctypes.byref(opt), ctypes.byref(srv)), "lnf_server_create")
     return srv
@@ -418,6 +422,23 @@ def lnf_filter_okada(h, vol, dims, dtype: int, t_d: int, out, stream=None) -> in
 def lnf_filter_entropy(h, vol, dims, dtype: int, radius: int, t_e: float, out, stream=None) -> int:
     return lib().lnf_filter_entropy(h, _p(vol), _dims_t(*[int(v) for v in dims]), dtype, radius,
                                     float(t_e), _p(out), stream_ptr(stream))
+
+
+def lnf_first_hit(h, vol, dims, dtype: int, threshold: int, direction: int, xyz,
+                  stream=None) -> int:
+    vp = vol if isinstance(vol, int) else vol.data_ptr()
+    xp = xyz if isinstance(xyz, int) else xyz.data_ptr()
+    return lib().lnf_first_hit(h, vp, _dims_t(*[int(v) for v in dims]), dtype, int(threshold),
+                               int(direction), xp, stream_ptr(stream))
+
+
+def lnf_filter_surface(h, vol, dims, dtype: int, radius: int, threshold: int, direction: int,
+                       xyz, out, stream=None) -> int:
+    vp = vol if isinstance(vol, int) else vol.data_ptr()
+    xp = xyz if isinstance(xyz, int) else xyz.data_ptr()
+    op = out if isinstance(out, int) else out.data_ptr()
+    return lib().lnf_filter_surface(h, vp, _dims_t(*[int(v) for v in dims]), dtype, int(radius),
+                                    int(threshold), int(direction), xp, op, stream_ptr(stream))
 
 
 def lnf_filter_points(h, vol, dims, dtype: int, radius: int, xyz, n: int, out, stream=None) -> int:

@@ -107,6 +107,33 @@ class Filter:
             raise LnfError(rc, "lnf_filter_points")
         return out
 
+    def first_hit(self, vol, threshold: int, direction: int = 1, stream=None):
+        """First voxel >= threshold along each z-ray (direction 1: from slice 0,
+        -1: from the last slice): int32 [ny*nx, 3] of (x, y, z), z = -1 for a miss."""
+        import torch
+        _require_cuda(vol, "vol")
+        nz, ny, nx = vol.shape
+        xyz = torch.empty((ny * nx, 3), dtype=torch.int32, device=vol.device)
+        rc = _lib.lnf_first_hit(self._h, vol, _lib.dims_of(vol), _lib.dtype_code(vol), threshold,
+                                direction, xyz, stream)
+        if rc != _lib.LNF_OK:
+            raise LnfError(rc, "lnf_first_hit")
+        return xyz
+
+    def surface(self, vol, radius: int, threshold: int, direction: int = 1, stream=None):
+        """The filter at each z-ray's first hit: (values [ny, nx] as int32 holding
+        uint32 bits, 0xFFFFFFFF for a miss; hits [ny*nx, 3])."""
+        import torch
+        _require_cuda(vol, "vol")
+        nz, ny, nx = vol.shape
+        xyz = torch.empty((ny * nx, 3), dtype=torch.int32, device=vol.device)
+        out = torch.empty((ny, nx), dtype=torch.int32, device=vol.device)
+        rc = _lib.lnf_filter_surface(self._h, vol, _lib.dims_of(vol), _lib.dtype_code(vol),
+                                     int(radius), threshold, direction, xyz, out, stream)
+        if rc != _lib.LNF_OK:
+            raise LnfError(rc, "lnf_filter_surface")
+        return out, xyz
+
     def histogram(self, vol, stream=None):
         import torch
         _require_cuda(vol, "vol")
@@ -180,10 +207,12 @@ class Server:
     """
 
     def __init__(self, filt: Filter, cap_bytes: int = 200 << 30, n_streams: int = 4,
-                 max_batch: int = 256, mode: int = _lib.LNF_SERVE_BATCHED, fail_batch: int = 0):
+                 max_batch: int = 256, mode: int = _lib.LNF_SERVE_BATCHED, fail_batch: int = 0,
+                 batch_mvox: int = 0):
+        """batch_mvox: voxel budget of a micro-batch in 2^20 voxels (0: 32)."""
         self.filt = filt
         self._s = _lib.lnf_server_create(filt.handle, mode, cap_bytes, n_streams, max_batch,
-                                         fail_batch)
+                                         fail_batch, batch_mvox)
         self._keep = []
 
     def put(self, host, dims=None, dtype=None, pitch=None, keep=None):

@@ -12,6 +12,16 @@
 // cluster sums (and sums of squares for MINVAR9) are combined with butterfly
 // wavefront reductions (cross-lane shuffles); MEAN9 needs only their total.
 // Lane 0 applies the rule, rounding and gate.
+//
+// The first-hit pass produces that point list for rays parallel to z: per
+// pixel (x, y), the first voxel of the column, in the ray's direction, whose
+// value reaches the threshold (the surface, Otsu's T in the paper).  One lane
+// per ray, 64 neighbouring x per wavefront, so every slice step of a
+// wavefront reads one contiguous row segment; each step issues kHitStep
+// independent slice loads before testing them, to keep enough reads in
+// flight for HBM.  A lane stops at its hit (its loads are masked off from
+// then on) and the wavefront at its deepest hit, so the bytes read are the
+// columns up to their hits.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -128,6 +138,58 @@ __global__ __launch_bounds__(64 * kWaves) void filter_points_kernel(const T* __r
     out[p] = o;
 }
 
+constexpr int kHitStep = 8;     // slices loaded per step of a ray
+constexpr int kHitRows = 4;     // wavefronts (pixel rows) per workgroup
+
+template <typename T, bool BACK>
+__global__ __launch_bounds__(64 * kHitRows) void first_hit_kernel(const T* __restrict__ in,
+                                                                  Geom g, uint32_t thr,
+                                                                  int tiles_x,
+                                                                  int32_t* __restrict__ xyz)
+{
+    const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+    const int x = bx * 64 + (threadIdx.x & 63);
+    const int y = by * kHitRows + (threadIdx.x >> 6);
+    if (x >= g.nx || y >= g.ny) return;
+    const size_t plane = (size_t)g.nx * g.ny;
+    const T* col = in + (size_t)y * g.nx + x;
+    int hit = -1;  // steps from the ray's first slice
+    for (int s0 = 0; s0 < g.nz; s0 += kHitStep) {
+        uint32_t v[kHitStep];
+#pragma unroll
+        for (int k = 0; k < kHitStep; ++k) {
+            const int s = s0 + k;
+            const int z = BACK ? g.nz - 1 - s : s;
+            v[k] = s < g.nz ? (uint32_t)col[(size_t)z * plane] : 0u;
+        }
+#pragma unroll
+        for (int k = kHitStep - 1; k >= 0; --k)  // the first qualifying step wins
+            if (s0 + k < g.nz && v[k] >= thr) hit = s0 + k;
+        if (hit >= 0) break;
+    }
+    int32_t* o = xyz + 3 * ((size_t)y * g.nx + x);
+    o[0] = x;
+    o[1] = y;
+    o[2] = hit < 0 ? -1 : (BACK ? g.nz - 1 - hit : hit);
+}
+
+template <typename T>
+hipError_t launch_first_hit(const void* vol, Geom g, uint32_t thr, int direction, int32_t* xyz,
+                            hipStream_t s)
+{
+    const int tiles_x = (g.nx + 63) / 64;
+    const long long blocks = (long long)tiles_x * ((g.ny + kHitRows - 1) / kHitRows);
+    const dim3 grid((unsigned)blocks), block(64 * kHitRows);
+    const T* in = static_cast<const T*>(vol);
+    if (direction > 0)
+        hipLaunchKernelGGL((first_hit_kernel<T, false>), grid, block, 0, s, in, g, thr, tiles_x,
+                           xyz);
+    else
+        hipLaunchKernelGGL((first_hit_kernel<T, true>), grid, block, 0, s, in, g, thr, tiles_x,
+                           xyz);
+    return hipGetLastError();
+}
+
 template <int R, typename T>
 hipError_t launch_points_r(int rule, const void* vol, Geom g, const int32_t* xyz, int64_t n,
                            uint32_t gate, uint32_t* out, hipStream_t s)
@@ -159,6 +221,61 @@ hipError_t launch_points(int rule, int r, const void* vol, Geom g, const int32_t
 }  // namespace lnf
 
 using namespace lnf;
+
+namespace {
+
+// Checks shared by the first-hit entry points: the volume and a hit list of
+// nx * ny entries on the context's device.
+int check_first_hit(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                    int direction, const int32_t* xyz, Geom* g)
+{
+    if (!h || !vol || !dims || !xyz) return LNF_EINVAL;
+    if (dtype != LNF_U8 && dtype != LNF_U16) return LNF_EINVAL;
+    if (direction != 1 && direction != -1) return LNF_EINVAL;
+    for (int i = 0; i < 3; ++i)
+        if (dims[i] < 1 || dims[i] > INT32_MAX) return LNF_EINVAL;
+    if (dims[0] * dims[1] > INT32_MAX) return LNF_EINVAL;
+    *g = Geom{(int)dims[0], (int)dims[1], (int)dims[2]};
+    const size_t bytes = (size_t)dims[0] * dims[1] * dims[2] * (dtype == LNF_U8 ? 1 : 2);
+    int rc;
+    if ((rc = check_device_range(vol, bytes, h->device))) return rc;
+    return check_device_range(xyz, (size_t)dims[0] * dims[1] * 3 * sizeof(int32_t), h->device);
+}
+
+}  // namespace
+
+extern "C" int lnf_first_hit(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                             uint32_t threshold, int direction, int32_t* xyz, hipStream_t stream)
+{
+    if (!h) return LNF_EINVAL;
+    DeviceGuard dg(h->device);
+    if (!dg.ok()) return LNF_EHIP;
+    Geom g;
+    const int rc = check_first_hit(h, vol, dims, dtype, direction, xyz, &g);
+    if (rc) return rc;
+    const hipError_t e = dtype == LNF_U8
+                             ? launch_first_hit<uint8_t>(vol, g, threshold, direction, xyz, stream)
+                             : launch_first_hit<uint16_t>(vol, g, threshold, direction, xyz, stream);
+    return e == hipSuccess ? LNF_OK : LNF_EHIP;
+}
+
+extern "C" int lnf_filter_surface(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
+                                  int radius, uint32_t threshold, int direction, int32_t* xyz,
+                                  uint32_t* out, hipStream_t stream)
+{
+    if (!h || !out) return LNF_EINVAL;
+    if (h->geom) return LNF_EINVAL;  // default cluster geometry only, as lnf_filter_points
+    if (radius < 1 || radius > LNF_RADIUS_MAX) return LNF_EINVAL;
+    DeviceGuard dg(h->device);
+    if (!dg.ok()) return LNF_EHIP;
+    Geom g;
+    int rc = check_first_hit(h, vol, dims, dtype, direction, xyz, &g);
+    if (rc) return rc;
+    const int64_t n = dims[0] * dims[1];
+    if ((rc = check_device_range(out, (size_t)n * sizeof(uint32_t), h->device))) return rc;
+    if ((rc = lnf_first_hit(h, vol, dims, dtype, threshold, direction, xyz, stream))) return rc;
+    return lnf_filter_points(h, vol, dims, dtype, radius, xyz, n, out, stream);
+}
 
 extern "C" int lnf_filter_points(lnf_handle h, const void* vol, const int64_t dims[3], int dtype,
                                  int radius, const int32_t* xyz, int64_t n, uint32_t* out,

@@ -5,9 +5,15 @@
 //     device footprint (resident volumes + outputs + cached free blocks) stays
 //     under the cap; to make room it drops cached blocks, then evicts idle
 //     resident volumes least-recently-used first;
-//   - micro-batching: everything admitted in one pass becomes one
-//     lnf_filter_batch launch on the next stream of the pool (after waiting on
-//     the upload events of its volumes), so later batches overlap earlier ones;
+//   - micro-batching: requests admitted in one pass, up to max_batch of them
+//     and the voxel budget, become one lnf_filter_batch launch on the next
+//     stream of the pool (after waiting on the upload events of its volumes),
+//     so later batches overlap earlier ones;
+//   - device queue bound: a pass launches only while fewer than two batches
+//     are in flight or their voxels stay under twice the budget.  Requests
+//     beyond that wait in the host queue, where they are batched with later
+//     arrivals, instead of piling up on the streams, where concurrent
+//     batches would share the device and all finish late;
 //   - completion: per-batch events are polled; latency is measured from each
 //     request's scheduled arrival time to the moment its completion is seen.
 // Device memory comes from an arena: chunks are allocated on demand up to the
@@ -181,13 +187,17 @@ struct Request {
 struct Flight {
     std::vector<uint64_t> tickets;
     hipEvent_t done = nullptr;
+    uint64_t voxels = 0;
 };
 
 }  // namespace
 
 class Server {
 public:
-    Server(lnf_handle h, const lnf_server_options& o) : h_(h), o_(o) {}
+    Server(lnf_handle h, const lnf_server_options& o)
+        : h_(h), o_(o), budget_((uint64_t)(o.batch_mvox > 0 ? o.batch_mvox : 32) << 20)
+    {
+    }
 
     int init()
     {
@@ -506,14 +516,20 @@ private:
         }
     }
 
-    // Admit pending requests in order while memory allows; returns the admitted.
+    // Whether another batch may go to the device now (the device queue bound).
+    bool may_launch() const { return flights_.size() < 2 || inflight_vox_ < 2 * budget_; }
+
+    // Admit pending requests in order while memory, max_batch and the voxel
+    // budget allow; returns the admitted.
     std::vector<uint64_t> admit()
     {
         std::vector<uint64_t> got;
         const int cap = o_.mode == LNF_SERVE_FIFO ? 1 : o_.max_batch;
+        uint64_t vox = 0;
         while (!pending_.empty() && (int)got.size() < cap) {
             const uint64_t t = pending_.front();
             Request& r = reqs_[t];
+            if (!got.empty() && vox + r.voxels > budget_) break;  // starts the next batch
             const Volume& v = vols_[r.vol];
             const size_t bytes = (size_t)r.voxels * (v.dtype == LNF_U8 ? 1 : 2);
             if (get_block(bytes, r.vol, &r.out, &r.block) != LNF_OK) {
@@ -529,6 +545,7 @@ private:
             r.state = kInFlight;
             pending_.pop_front();
             got.push_back(t);
+            vox += r.voxels;
         }
         return got;
     }
@@ -575,6 +592,7 @@ private:
         }
         Flight f;
         f.tickets = ts;
+        for (uint64_t t : ts) f.voxels += reqs_[t].voxels;
         if (rc == LNF_OK) rc = take_event(&f.done);
         if (rc == LNF_OK && hipEventRecord(f.done, s) != hipSuccess) rc = LNF_EHIP;
         if (rc != LNF_OK) {
@@ -586,6 +604,7 @@ private:
             done_cv_.notify_all();
             return;
         }
+        inflight_vox_ += f.voxels;
         flights_.push_back(std::move(f));
     }
 
@@ -603,6 +622,7 @@ private:
             if (q != hipSuccess) (void)hipGetLastError();
             for (uint64_t t : it->tickets) finish(t, status, now);
             free_events_.push_back(it->done);
+            inflight_vox_ -= it->voxels;
             it = flights_.erase(it);
             any = true;
         }
@@ -616,7 +636,7 @@ private:
         std::unique_lock<std::mutex> lk(mu_);
         while (true) {
             bool progress = reap();
-            if (!pending_.empty()) {
+            if (!pending_.empty() && may_launch()) {
                 std::vector<uint64_t> ts = admit();
                 if (!ts.empty()) {
                     launch(ts);
@@ -636,6 +656,8 @@ private:
 
     lnf_handle h_;
     lnf_server_options o_;
+    uint64_t budget_;            // voxel budget of one micro-batch
+    uint64_t inflight_vox_ = 0;  // voxels of the batches in flight
     std::mutex mu_;
     std::condition_variable cv_, done_cv_;
     std::thread worker_;
@@ -683,7 +705,7 @@ int lnf_server_create(lnf_handle h, const lnf_server_options* opt, lnf_server_ha
     }
     if ((o.mode != LNF_SERVE_BATCHED && o.mode != LNF_SERVE_FIFO) || o.cap_bytes == 0 ||
         o.n_streams < 1 || o.n_streams > 16 || o.max_batch < 1 || o.max_batch > LNF_BATCH_MAX ||
-        o.fail_batch < 0)
+        o.fail_batch < 0 || o.batch_mvox < 0 || o.batch_mvox > (1 << 20))
         return LNF_EINVAL;
     Server* s = new (std::nothrow) Server(h, o);
     if (!s) return LNF_ENOMEM;

@@ -224,3 +224,67 @@ def test_cancel_wakes_a_waiting_thread():
                 return
             assert rc == _lib.LNF_EBUSY and res["rc"] == 0  # it had already started
         pytest.skip("the request always started before it could be cancelled")
+
+
+def test_micro_batches_keep_the_voxel_budget():
+    """With a budget of 2^20 voxels, requests on 96^3 volumes (884,736 voxels)
+    can never share a micro-batch, and 32^3 ones at most 32 to a batch."""
+    big = ph.ct_u12((96, 96, 96), seed=31)
+    small = ph.ct_u12((32, 32, 32), seed=32)
+    with _filter() as f, _server(f, max_batch=256, batch_mvox=1) as s:
+        rc_b, vb = s.put(_pinned(big))
+        rc_s, vs = s.put(_pinned(small))
+        assert rc_b == 0 and rc_s == 0
+        s.sync()
+        s.stats(reset=True)
+        n = 12
+        tickets = [s.submit(vb, 1 + k % 3)[1] for k in range(n)]
+        s.sync()
+        assert all(s.wait(t, 1000) == 0 for t in tickets)
+        assert s.stats(reset=True)["batches"] == n
+        tickets = [s.submit(vs, 1 + k % 3)[1] for k in range(200)]
+        s.sync()
+        assert all(s.wait(t, 1000) == 0 for t in tickets)
+        assert s.stats()["batches"] >= -(-200 // 32)
+    with _filter() as f:
+        with pytest.raises(_lib.LnfError):
+            _server(f, batch_mvox=-1)
+
+
+@pytest.mark.timeout(600)
+def test_results_same_alone_and_in_the_mix_large_volumes():
+    """Benchmark-sized volumes (sides 128..512) through the batched server with
+    mixed radii and both voxel types: every output equals the volume filtered
+    alone, and sampled voxels equal the oracle."""
+    rng = np.random.default_rng(41)
+    dims = [(128, 128, 128), (200, 160, 144), (320, 256, 192), (512, 512, 512), (250, 130, 170)]
+    vols = [ph.ct_u12(d, seed=4100 + i, device="cuda").cpu().numpy() if i != 4
+            else ph.small_u8(4104, dims=d) for i, d in enumerate(dims)]
+    with _filter() as f, _server(f, n_streams=4, max_batch=64) as s:
+        ids = []
+        for v in vols:
+            rc, vid = s.put(_pinned(v))
+            assert rc == 0
+            ids.append(vid)
+        reqs = []
+        for k in range(14):
+            i = k % len(vols) if k < len(vols) else int(rng.integers(0, len(vols)))
+            r = int(rng.integers(1, 4))
+            out = _empty_pinned_like(torch.from_numpy(vols[i]))
+            rc, t = s.submit(ids[i], r, host_out=out)
+            assert rc == 0
+            reqs.append((t, i, r, out))
+        for t, i, r, out in reqs:
+            assert s.wait(t, 120000) == 0
+            got = out.numpy()
+            alone = f(torch.from_numpy(vols[i]).cuda(), r).cpu().numpy()
+            assert np.array_equal(got, alone), f"volume {dims[i]} r={r}"
+            nz, ny, nx = vols[i].shape
+            pts = np.stack([rng.integers(0, nx, 400), rng.integers(0, ny, 400),
+                            rng.integers(0, nz, 400)], 1)
+            pts[:8] = [[0, 0, 0], [nx - 1, ny - 1, nz - 1], [0, ny - 1, 0], [nx - 1, 0, nz - 1],
+                       [nx // 2, 0, nz // 2], [0, ny // 2, nz - 1], [nx - 1, ny // 2, 0],
+                       [nx // 2, ny // 2, nz // 2]]
+            want = oracle.filter_points(vols[i], r, pts)
+            assert np.array_equal(got[pts[:, 2], pts[:, 1], pts[:, 0]].astype(np.uint32), want)
+        assert s.stats()["completed"] == 14
