@@ -151,32 +151,36 @@ def test_full_512_cube(c2_volume, rule, r):
 
 @pytest.mark.timeout(900)
 def test_scale_volume_strip_seams():
-    """1024 x 1024 x 1536 at r = 3: whole z-slices on both sides of every
-    default z-strip seam, and the first and last slices, for both rules."""
+    """1024 x 1024 x 1536 at r = 3, both rules: the default launch (whose x-y
+    tiles alone fill the GPU, so it runs one z-strip per column) and the same
+    tile forced into 384-slice z-strips.  Whole z-slices on both sides of every
+    seam, plus the first, middle and last slices, against the oracle."""
     from paper_1807_03119_amd.api import Filter
     dims = (1024, 1024, 1536)
     dev = ph.ct_u12(dims, seed=3000, device="cuda")
     out = torch.empty_like(dev)
     host = None
     nx, ny, nz = dims
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
     for rc, oc in ((_lib.LNF_MEAN9, oracle.MEAN9), (_lib.LNF_MINVAR9, oracle.MINVAR9)):
         with Filter(rc, 0) as f:
-            _variant, zs = f.tile_config(dims, _lib.LNF_U16, 3)
-            f(dev, 3, out=out)
-            torch.cuda.synchronize()
-            if host is None:
-                host = dev.cpu().numpy()
-            seams = list(range(zs, nz, zs))
-            assert seams, "the default launch of this volume has several z-strips"
-            zsl = sorted({0, nz - 1} | {z for s in seams for z in (s - 1, s)})
-            yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
-            for z in zsl:
-                pts = np.stack([xx.ravel(), yy.ravel(), np.full(xx.size, z)], 1)
-                want = oracle.filter_points(host, 3, pts, oc).reshape(ny, nx)
-                got = out[z].cpu().numpy().astype(np.uint32)
-                if not np.array_equal(got, want):
-                    bad = np.argwhere(got != want)
-                    raise AssertionError(f"rule {rc} zs {zs} slice {z}: {len(bad)} differ, "
-                                         f"first (y,x)={tuple(bad[0])}")
+            variant, zs_default = f.tile_config(dims, _lib.LNF_U16, 3)
+            for zs in sorted({zs_default, 384}):
+                f(dev, 3, out=out, variant=variant, zs=zs)
+                torch.cuda.synchronize()
+                if host is None:
+                    host = dev.cpu().numpy()
+                seams = list(range(zs, nz, zs))
+                assert zs == zs_default or len(seams) == 3
+                zsl = sorted({0, nz // 2, nz - 1} | {z for s in seams for z in (s - 1, s)})
+                print(f"rule {rc} variant {variant} zs {zs}: slices {zsl}", flush=True)
+                for z in zsl:
+                    pts = np.stack([xx.ravel(), yy.ravel(), np.full(xx.size, z)], 1)
+                    want = oracle.filter_points(host, 3, pts, oc).reshape(ny, nx)
+                    got = out[z].cpu().numpy().astype(np.uint32)
+                    if not np.array_equal(got, want):
+                        bad = np.argwhere(got != want)
+                        raise AssertionError(f"rule {rc} zs {zs} slice {z}: {len(bad)} differ, "
+                                             f"first (y,x)={tuple(bad[0])}")
     del dev, out
     torch.cuda.empty_cache()
