@@ -57,6 +57,7 @@ extern "C" {
 #define LNF_ENOTFOUND (-6)  /* server: unknown volume id or ticket */
 #define LNF_ECANCELED (-7)  /* server: request was cancelled or its batch failed */
 #define LNF_ETIMEDOUT (-8)  /* server: wait timed out (request still pending) */
+#define LNF_ERANGE (-9)     /* more jobs than lnf_filter_batch_noalloc's static table holds */
 
 /* ---- enumerations ---------------------------------------------------- */
 #define LNF_U8 1            /* uint8 voxels */
@@ -201,6 +202,28 @@ LNF_API int lnf_filter_batch(lnf_handle h, const lnf_job* jobs, int n, hipStream
  */
 LNF_API int lnf_filter_batch_mode(lnf_handle h, const lnf_job* jobs, int n, hipStream_t stream,
                                   int mode);
+
+#define LNF_BATCH_NOALLOC_MAX 256 /* most jobs one lnf_filter_batch_noalloc call accepts */
+
+/*
+ * lnf_filter_batch (grid mode) for callers that cannot allocate device memory
+ * during the call: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The call allocates nothing: its job table
+ * is a static device array of the library (one per GPU, 12,544 bytes for
+ * LNF_BATCH_NOALLOC_MAX jobs, held until the process ends), filled from a
+ * host staging slot that lnf_create preallocated; the caller passes the
+ * inputs and outputs as for lnf_filter_batch, and the results are the same
+ * bytes.  Every call on a GPU, from any context, shares that one table, which
+ * keeps the last call's contents: calls whose work overlaps on one GPU
+ * (launched on different streams, or from different threads, without
+ * ordering between them) race on it and must be serialised by the caller;
+ * calls on one stream are ordered by the stream.  A captured call replays
+ * into the same table, so the same rule holds for graph replays.
+ * Errors: LNF_ERANGE (n > LNF_BATCH_NOALLOC_MAX); otherwise as
+ * lnf_filter_batch.
+ */
+LNF_API int lnf_filter_batch_noalloc(lnf_handle h, const lnf_job* jobs, int n,
+                                     hipStream_t stream);
 
 /*
  * Autotune: for every distinct (dtype, radius, volume-size class) among the

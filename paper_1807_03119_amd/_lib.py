@@ -22,6 +22,8 @@ LNF_EBUSY = -5
 LNF_ENOTFOUND = -6
 LNF_ECANCELED = -7
 LNF_ETIMEDOUT = -8
+LNF_ERANGE = -9
+LNF_BATCH_NOALLOC_MAX = 256
 
 LNF_U8 = 1
 LNF_U16 = 2
@@ -92,6 +94,7 @@ def _declare(lib):
         "lnf_tile_config": [_vp, ctypes.POINTER(ctypes.c_int64), _i32, _i32, ctypes.POINTER(lnf_tile)],
         "lnf_filter_batch": [_vp, ctypes.POINTER(lnf_job), _i32, _vp],
         "lnf_filter_batch_mode": [_vp, ctypes.POINTER(lnf_job), _i32, _vp, _i32],
+        "lnf_filter_batch_noalloc": [_vp, ctypes.POINTER(lnf_job), _i32, _vp],
         "lnf_tune": [_vp, ctypes.POINTER(lnf_job), _i32],
         "lnf_tune_save": [_vp, ctypes.c_char_p],
         "lnf_tune_load": [_vp, ctypes.c_char_p],
@@ -282,6 +285,15 @@ def lnf_filter_batch(h, jobs, n=None, stream=None, mode=None) -> int:
     if mode is None:
         return lib().lnf_filter_batch(h, jobs, n, stream_ptr(stream))
     return lib().lnf_filter_batch_mode(h, jobs, n, stream_ptr(stream), int(mode))
+
+
+def lnf_filter_batch_noalloc(h, jobs, n=None, stream=None) -> int:
+    """`jobs`: a make_jobs array (or a list accepted by make_jobs)."""
+    if isinstance(jobs, (list, tuple)):
+        n = len(jobs) if n is None else n
+        jobs = make_jobs(jobs)
+    n = len(jobs) if n is None else n
+    return lib().lnf_filter_batch_noalloc(h, jobs, n, stream_ptr(stream))
 
 
 def lnf_tune(h, jobs, n=None) -> int:

@@ -202,6 +202,7 @@ const char* lnf_strerror(int code)
     case LNF_ENOTFOUND: return "unknown volume id or ticket";
     case LNF_ECANCELED: return "request cancelled or failed";
     case LNF_ETIMEDOUT: return "timed out";
+    case LNF_ERANGE: return "more jobs than the static job table of lnf_filter_batch_noalloc holds";
     default: return "unknown status code";
     }
 }

@@ -25,6 +25,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -136,6 +137,40 @@ ClassKernel class_kernel(int rule, int c, bool gate, int variant, bool queue)
                    : class_kernel_t<uint8_t>(rule, r, gate, variant, queue);
 }
 
+// ---- job table of lnf_filter_batch_noalloc ----------------------------------
+// A file-scope device array: one copy per GPU, at its own address on each,
+// kept until the process ends.  In host code the name `scratch` is only a
+// host-side stand-in; host code uses the device address that
+// hipGetSymbolAddress returns for the current device (static_table_init).
+struct StaticBatchTable {
+    BatchClass c[kClasses];
+    BatchJobDesc jobs[LNF_BATCH_NOALLOC_MAX];
+};
+static_assert(offsetof(StaticBatchTable, jobs) == offsetof(BatchTable, jobs),
+              "the static table is a prefix of BatchTable");
+static_assert(sizeof(StaticBatchTable) == 12544, "size stated in lnf.h");
+static __device__ __align__(256) unsigned char scratch[sizeof(StaticBatchTable)];
+
+std::mutex g_static_mu;
+std::map<int, BatchTable*> g_static_table;  // device -> address of its `scratch`
+
+// Address of `scratch` on `device`, which must be the current device; looked
+// up once per device.  Null when the lookup fails.
+BatchTable* static_table_init(int device)
+{
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    auto it = g_static_table.find(device);
+    if (it != g_static_table.end()) return it->second;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    BatchTable* t = static_cast<BatchTable*>(p);
+    g_static_table[device] = t;
+    return t;
+}
+
 struct BatchSlot {
     BatchTable* host = nullptr;  // pinned staging copy of the table
     BatchTable* dev = nullptr;
@@ -154,6 +189,7 @@ struct BatchState {
     // the rest (no allocation may happen during a capture) and never reused.
     BatchSlot captured[kCaptureSlots];
     int ncaptured = 0;
+    BatchTable* static_dev = nullptr;  // this device's `scratch` (lnf_filter_batch_noalloc)
 };
 
 namespace {
@@ -192,6 +228,9 @@ int batch_state_init(lnf_ctx* h)
         if (int rc = build_slot(s)) return rc;
     for (auto& s : st->captured)
         if (int rc = build_slot(s)) return rc;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || !(st->static_dev = static_table_init(dev)))
+        return LNF_EHIP;
     return LNF_OK;
 }
 
@@ -232,8 +271,9 @@ int validate_jobs(const lnf_ctx* h, const lnf_job* jobs, int n, std::vector<Geom
     return LNF_OK;
 }
 
+// dev_table: where the table goes on the device (null: the slot's own buffer).
 int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>& geoms,
-                 hipStream_t stream, bool queue)
+                 hipStream_t stream, bool queue, BatchTable* dev_table = nullptr)
 {
     BatchState* st = h->batch;
     if (!st) return LNF_ENOMEM;
@@ -340,11 +380,11 @@ int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>
         k = kend;
     }
     const size_t used = offsetof(BatchTable, jobs) + (size_t)std::max(n, 1) * sizeof(BatchJobDesc);
-    if (hipMemcpyAsync(s.dev, s.host, used, hipMemcpyHostToDevice, stream) != hipSuccess)
+    BatchTable* dtab = dev_table ? dev_table : s.dev;
+    if (hipMemcpyAsync(dtab, s.host, used, hipMemcpyHostToDevice, stream) != hipSuccess)
         return LNF_EHIP;
     for (int c = 0; c < kClasses; ++c) {
         if (tab->c[c].total == 0) continue;
-        BatchTable* dtab = s.dev;
         int cls = c;
         uint32_t gate = h->gate;
         hipError_t e;
@@ -390,4 +430,21 @@ extern "C" int lnf_filter_batch_mode(lnf_handle h, const lnf_job* jobs, int n, h
 extern "C" int lnf_filter_batch(lnf_handle h, const lnf_job* jobs, int n, hipStream_t stream)
 {
     return lnf_filter_batch_mode(h, jobs, n, stream, LNF_BATCH_GRID);
+}
+
+// Grid mode with the job table in this GPU's static `scratch` array: no
+// allocation of any kind on the device (the host staging slot and the table
+// address were set up by lnf_create).
+extern "C" int lnf_filter_batch_noalloc(lnf_handle h, const lnf_job* jobs, int n,
+                                        hipStream_t stream)
+{
+    if (!h) return LNF_EINVAL;
+    if (n > LNF_BATCH_NOALLOC_MAX) return LNF_ERANGE;
+    std::vector<Geom> geoms;
+    DeviceGuard dg(h->device);
+    if (!dg.ok()) return LNF_EHIP;
+    int rc = validate_jobs(h, jobs, n, &geoms);
+    if (rc || n == 0) return rc;
+    if (!h->batch || !h->batch->static_dev) return LNF_EHIP;
+    return batch_launch(h, jobs, n, geoms, stream, false, h->batch->static_dev);
 }

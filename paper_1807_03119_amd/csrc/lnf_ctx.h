@@ -28,7 +28,7 @@ struct lnf_ctx {
     mutable std::mutex mu;  // guards `tuned`
     std::unordered_map<lnf::TuneKey, lnf::TileCfg> tuned;
     void* dev_state = nullptr;  // library-internal device memory (see ctx_init_device_state)
-    lnf::BatchState* batch = nullptr;  // created on the first lnf_filter_batch call
+    lnf::BatchState* batch = nullptr;  // job-table slots of lnf_filter_batch (lnf_create)
     std::mutex otsu_mu;                 // guards the Otsu scratch below
     uint64_t* otsu_dev = nullptr;       // 65536 histogram counters (lnf_filter_otsu)
     uint64_t* otsu_host = nullptr;      // pinned copy read by the host
