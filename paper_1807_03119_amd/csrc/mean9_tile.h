@@ -149,11 +149,13 @@ constexpr bool m9_packed_may_overflow()
     return (uint64_t)(4 * R + 2) * ((1u << (8 * sizeof(T))) - 1u) >= 65536u;
 }
 
-// inv_div: 1/(9n), or 1/n with kM9Box.  Returns false when a kM9Packed tile
-// stopped because some qx did not fit 16 bits; its outputs are then
-// incomplete and the tile must be filtered again in kM9Exact.
+// inv_div: 1/(9n), or 1/n with kM9Box.  Returns z1 when every output slice
+// of [z0, z1) is final.  A kM9Packed tile that stopped because some qx did
+// not fit 16 bits returns the first output slice that may be wrong instead:
+// the slices before it are final, and the rest must be filtered again in
+// kM9Exact from that slice on.
 template <int R, int TY, typename T, bool GATE, int TXW, bool PK, int MODE>
-__device__ __forceinline__ bool mean9_tile_body(M9Smem<R, TY, TXW, PK, MODE>& sm,
+__device__ __forceinline__ int mean9_tile_body(M9Smem<R, TY, TXW, PK, MODE>& sm,
                                                 const T* __restrict__ in, T* __restrict__ out,
                                                 Geom g, int x0, int y0, int z0, int z1,
                                                 uint32_t gate, double inv_div, int tid)
@@ -317,7 +319,7 @@ __device__ __forceinline__ bool mean9_tile_body(M9Smem<R, TY, TXW, PK, MODE>& sm
     }
     wait_vmem_le<S::VMWAIT>();
     barrier_lds();
-    bool ok = true;
+    int zdone = z1;
     // iteration k: x-pass of slice k, y-pass of slice k-1 and its outputs;
     // whole blocks of D iterations (no exit inside the unrolled block)
     for (int kb = 0; kb <= ns; kb += D) {
@@ -390,11 +392,14 @@ __device__ __forceinline__ bool mean9_tile_body(M9Smem<R, TY, TXW, PK, MODE>& sm
         }
         if constexpr (kCheck) {
             // block end: publish any qx >= 2^16 formed so far, then stop the
-            // whole workgroup if some thread saw one
+            // whole workgroup if some thread saw one.  The previous check
+            // cleared the x-passes of iterations before kb, and the outputs of
+            // iteration k read the x-pass of iteration k-1 only, so outputs of
+            // iterations up to kb are final
             if (qor >> 16) sm.flag = 1;
             barrier_lds();
             if (sm.flag) {
-                ok = false;
+                zdone = max(z0, z0 + kb - 1 - LAG);
                 break;
             }
         }
@@ -402,7 +407,7 @@ __device__ __forceinline__ bool mean9_tile_body(M9Smem<R, TY, TXW, PK, MODE>& sm
     // drain the staging of the slices past the end before the LDS is reused
     wait_vmem();
     barrier_lds();
-    return ok;
+    return zdone;
 }
 
 // Whether packed mode can stop, so that a kernel needs the unpacked bodies.
@@ -427,7 +432,8 @@ union M9SmemAny {
 
 // One tile; `pairs` (mean9_pairs_ok for the volume) selects paired staging
 // for the tiles whose x halo stays inside the volume.  MEAN9 runs packed and,
-// where that can stop, again unpacked for a tile whose packed run stopped.
+// where that can stop, unpacked from the first slice a stopped packed run
+// left unfinished.
 // tid: threadIdx.x (see tile_tid for loops over several tiles).
 template <int R, int TY, typename T, bool GATE, int TXW = 64, bool BOX = false>
 __device__ __forceinline__ void mean9_tile(M9SmemAny<R, TY, TXW, T, BOX>& sm, bool pairs,
@@ -438,19 +444,19 @@ __device__ __forceinline__ void mean9_tile(M9SmemAny<R, TY, TXW, T, BOX>& sm, bo
     constexpr int H = 2 * R, LXE = TXW + 4 * R;
     constexpr int kMode = BOX ? kM9Box : kM9Packed;
     if (pairs && x0 - H >= 0 && x0 - H + LXE <= g.nx) {
-        if (mean9_tile_body<R, TY, T, GATE, TXW, true, kMode>(sm.p, in, out, g, x0, y0, z0, z1,
-                                                              gate, inv_div, tid))
-            return;
+        const int zr = mean9_tile_body<R, TY, T, GATE, TXW, true, kMode>(
+            sm.p, in, out, g, x0, y0, z0, z1, gate, inv_div, tid);
         if constexpr (m9_needs_exact<T, R, BOX>())
-            mean9_tile_body<R, TY, T, GATE, TXW, true, kM9Exact>(sm.px, in, out, g, x0, y0, z0, z1,
-                                                                 gate, inv_div, tid);
+            if (zr < z1)
+                mean9_tile_body<R, TY, T, GATE, TXW, true, kM9Exact>(sm.px, in, out, g, x0, y0, zr,
+                                                                     z1, gate, inv_div, tid);
     } else {
-        if (mean9_tile_body<R, TY, T, GATE, TXW, false, kMode>(sm.e, in, out, g, x0, y0, z0, z1,
-                                                               gate, inv_div, tid))
-            return;
+        const int zr = mean9_tile_body<R, TY, T, GATE, TXW, false, kMode>(
+            sm.e, in, out, g, x0, y0, z0, z1, gate, inv_div, tid);
         if constexpr (m9_needs_exact<T, R, BOX>())
-            mean9_tile_body<R, TY, T, GATE, TXW, false, kM9Exact>(sm.ex, in, out, g, x0, y0, z0,
-                                                                  z1, gate, inv_div, tid);
+            if (zr < z1)
+                mean9_tile_body<R, TY, T, GATE, TXW, false, kM9Exact>(sm.ex, in, out, g, x0, y0,
+                                                                      zr, z1, gate, inv_div, tid);
     }
 }
 

@@ -73,6 +73,26 @@ def test_wide_mean9_every_variant(kind):
                     _same(got, want, f"{kind} r={r} variant {variant} zs {zs}")
 
 
+@pytest.mark.parametrize("slab", [(50, 3), (9, 1), (93, 3)])
+def test_wide_mean9_falls_back_mid_strip(slab):
+    """A dim volume with a bright slab deep in z: packed tiles stop at the
+    slab and rerun unpacked from there, keeping the slices before it.  Every
+    variant, z-strips of the default, 7 and 40 slices, r = 1..4."""
+    from paper_1807_03119_amd.api import Filter
+    z, depth = slab
+    rng = np.random.default_rng(17 + z)
+    vol = rng.integers(0, 1024, (96, 40, 200), dtype=np.uint16)
+    vol[z:z + depth, 5:30, 20:180] = rng.integers(60000, 65536, (depth, 25, 160), dtype=np.uint16)
+    dev = _dev(vol)
+    with Filter(_lib.LNF_MEAN9, 0) as f:
+        for r in range(1, _lib.LNF_RADIUS_MAX + 1):
+            want = oracle.filter_volume(vol, r)
+            for variant in [-1] + list(range(_lib.lnf_tile_variants(_lib.LNF_MEAN9, _lib.LNF_U16, r))):
+                for zs in (0, 7, 40):
+                    got = f(dev, r, variant=variant, zs=zs).cpu().numpy()
+                    _same(got, want, f"slab {slab} r={r} variant {variant} zs {zs}")
+
+
 @pytest.mark.parametrize("kind", ["u12_hot", "u16"])
 def test_wide_mean9_gated(kind):
     """The gate applies after the packed and the unpacked runs alike."""
