@@ -33,14 +33,16 @@ LIB_PATH = os.path.join(_HERE, "liblnf_oracle.so")
 _lib = None
 
 
-def build() -> str:
-    """Compile the oracle with gcc (always recompiles)."""
-    tmp = LIB_PATH + ".tmp"
+def build(src: str = _SRC, out: str = LIB_PATH) -> str:
+    """Compile the oracle with gcc (always recompiles).  The tests also compile
+    deliberately broken copies of the source this way, to show that the pins
+    catch them."""
+    tmp = out + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-Wall", "-Wextra",
-           "-o", tmp, _SRC]
+           "-o", tmp, src]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 def _load():
@@ -49,7 +51,13 @@ def _load():
         return _lib
     if not os.path.exists(LIB_PATH):
         build()
-    lib = ctypes.CDLL(LIB_PATH)
+    _lib = open_library(LIB_PATH)
+    return _lib
+
+
+def open_library(path: str):
+    """ctypes handle of a compiled oracle, with its argument types set."""
+    lib = ctypes.CDLL(path)
     i64, vp = ctypes.c_int64, ctypes.c_void_p
     lib.lnfo_filter.argtypes = [vp, i64, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                 ctypes.c_uint32, vp]
@@ -68,7 +76,6 @@ def _load():
     for f in (lib.lnfo_filter, lib.lnfo_filter_geom, lib.lnfo_filter_points,
               lib.lnfo_cluster_stats, lib.lnfo_cluster_stats_geom, lib.lnfo_threads):
         f.restype = ctypes.c_int
-    _lib = lib
     return lib
 
 

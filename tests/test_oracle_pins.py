@@ -255,10 +255,14 @@ def test_shift_and_complement(rule, r):
 
 
 def test_gate_writes_zero_below_threshold():
+    """Outputs below T become 0; an output equal to T is kept (thresholds
+    include values the output takes)."""
     vol = ph.small_u8(seed=1004, dims=(16, 16, 16))
     for rule in (oracle.MEAN9, oracle.MINVAR9):
         plain = oracle.filter_volume(vol, 1, rule)
-        for t in (0, 1, 50, 101, 255, 256):
+        taken = (int(plain.min()), int(np.median(plain)), int(plain.max()))
+        assert all(np.count_nonzero(plain == t) for t in taken)
+        for t in (0, 1, 50, 101, 255, 256) + taken:
             gated = oracle.filter_volume(vol, 1, rule, gate=t)
             want = np.where(plain >= t, plain, 0)
             np.testing.assert_array_equal(gated, want)
