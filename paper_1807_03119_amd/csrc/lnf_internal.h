@@ -58,8 +58,9 @@ void minvar9_tile_shape(int variant, int r, int* tx, int* ty);  // output tile o
 hipError_t launch_minvar9(const void* in, void* out, int dtype, int r, Geom g, uint32_t gate,
                           TileCfg cfg, hipStream_t s, TileCfg* plan = nullptr);
 
-// Default z-strip depth: nz split into enough strips that tiles_xy * strips
-// reaches target_groups (strips no shallower than 16 slices).
+// Default z-strip depth: the strip count that minimises (rounds of
+// target_groups resident workgroups over tiles_xy * strips) x (strip depth +
+// 12 halo slices), strips at least 16 slices deep.
 int default_zs(int tiles_xy, int nz, int target_groups);
 // Workgroups of `kernel` (launched with `threads` threads, no dynamic LDS) that
 // the current device holds at once: CUs x resident workgroups per CU.

@@ -43,8 +43,9 @@
 //              up to 65535 / (4r+2): uint8, or 12-bit data up to r = 3), so
 //              the x-pass ORs together every qx it forms; at the end of each
 //              block of D slices the workgroup checks the OR, and a tile that
-//              saw qx >= 2^16 stops: the caller filters it again in kM9Exact,
-//              which rewrites every output of the tile.  Exact for every input.
+//              saw qx >= 2^16 stops: the caller filters it again in kM9Exact
+//              from the first output slice that may hold a wrong value on.
+//              Exact for every input.
 //   kM9Exact   px and qx in separate uint32 LDS words.
 //   kM9Box     the box term alone (the paper's mean filter, eq. 4): px only,
 //              S(z) = sum_{t=z-r..z+r} P(t).
