@@ -36,7 +36,7 @@ PROFILES = {
     "mean9": ("profiles/mean9_stream_r3_512cube_u16.txt",
               ["mean9.hip", "mean9_tile.h", "device_common.h", "lnf_internal.h"]),
     "minvar9": ("profiles/minvar9_planes_r3_512cube_u16.txt",
-                ["minvar9.hip", "minvar9_tile.h", "plane_tile.h", "device_common.h",
+                ["minvar9.hip", "plane_tile.h", "device_common.h",
                  "lnf_internal.h"]),
 }
 

@@ -35,7 +35,7 @@
 #include "lnf_internal.h"
 #include "batch_table.h"
 #include "mean9_tile.h"
-#include "minvar9_tile.h"
+#include "plane_tile.h"
 
 namespace lnf {
 
@@ -71,9 +71,9 @@ __attribute__((amdgpu_waves_per_eu((MV9Shape<R, WT>::WAVES)))) void minvar9_mult
     constexpr int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
     for_class_tiles<S::TX, S::TY, QUEUE>(tab, cls, &s_t, [&](const BatchJobDesc& d, int x0,
                                                             int y0, int z0, int z1, int tid) {
-        minvar9_tile<R, T, GATE, WT>(sm, static_cast<const T*>(d.in), static_cast<T*>(d.out),
-                                     Geom{d.nx, d.ny, d.nz}, x0, y0, z0, z1, gate, (double)n,
-                                     1.0 / n, tid);
+        plane_tile<R, R, kClusterBox, kRuleMinVar9, T, GATE, WT>(
+            sm, static_cast<const T*>(d.in), static_cast<T*>(d.out), Geom{d.nx, d.ny, d.nz}, x0,
+            y0, z0, z1, gate, (double)n, 1.0 / n, tid);
     });
 }
 

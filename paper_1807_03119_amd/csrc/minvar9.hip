@@ -1,8 +1,8 @@
 // MINVAR9 single-volume kernel: a thin wrapper around the tile body of
-// minvar9_tile.h (least-variance selection among the nine clusters).
+// plane_tile.h (least-variance selection among the nine clusters).
 #include "device_common.h"
 #include "lnf_internal.h"
-#include "minvar9_tile.h"
+#include "plane_tile.h"
 
 namespace lnf {
 namespace {
@@ -21,8 +21,9 @@ __attribute__((amdgpu_waves_per_eu(MV9Shape<R, WT>::WAVES))) void minvar9_planes
     const int by = rest % tiles_y;
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
-    minvar9_tile<R, T, GATE, WT>(sm, in, out, g, bx * S::TX, by * S::TY, z0, min(z0 + zs, g.nz),
-                                 gate, dn, invn, (int)threadIdx.x);
+    plane_tile<R, R, kClusterBox, kRuleMinVar9, T, GATE, WT>(
+        sm, in, out, g, bx * S::TX, by * S::TY, z0, min(z0 + zs, g.nz), gate, dn, invn,
+        (int)threadIdx.x);
 }
 
 template <int R, typename T, bool WT>

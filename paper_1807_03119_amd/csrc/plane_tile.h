@@ -550,4 +550,12 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
     }
 }
 
+// The paper's cluster geometry (cubes, diagonal offset r) under MINVAR9, as
+// the single-volume and the batch kernels run it.  WT: the wide-tile variant
+// (64 x 16 outputs, 512 threads, up to r = 3).
+template <int R, bool WT = false>
+using MV9Shape = PTShape<R, R, kClusterBox, kRuleMinVar9, WT>;
+template <int R, typename T, bool WT = false>
+using MV9Smem = PTSmem<R, R, kClusterBox, kRuleMinVar9, T, WT>;
+
 }  // namespace lnf
