@@ -209,7 +209,7 @@ LNF_API int lnf_filter_batch_mode(lnf_handle h, const lnf_job* jobs, int n, hipS
  * lnf_filter_batch (grid mode) for callers that cannot allocate device memory
  * during the call: code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc.  The call allocates nothing: its job table
- * is a static device array of the library (one per GPU, 12,544 bytes for
+ * is a static device array of the library (one per GPU, 12,672 bytes for
  * LNF_BATCH_NOALLOC_MAX jobs, held until the process ends), filled from a
  * host staging slot that lnf_create preallocated; the caller passes the
  * inputs and outputs as for lnf_filter_batch, and the results are the same

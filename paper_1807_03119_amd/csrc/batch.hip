@@ -148,7 +148,7 @@ struct StaticBatchTable {
 };
 static_assert(offsetof(StaticBatchTable, jobs) == offsetof(BatchTable, jobs),
               "the static table is a prefix of BatchTable");
-static_assert(sizeof(StaticBatchTable) == 12544, "size stated in lnf.h");
+static_assert(sizeof(StaticBatchTable) == 12672, "size stated in lnf.h");
 static __device__ __align__(256) unsigned char scratch[sizeof(StaticBatchTable)];
 
 std::mutex g_static_mu;
@@ -312,7 +312,7 @@ int batch_launch(lnf_ctx* h, const lnf_job* jobs, int n, const std::vector<Geom>
     int k = 0;
     for (int c = 0; c < kClasses; ++c) {
         BatchClass& cl = tab->c[c];
-        cl = BatchClass{0, 0, k, 0, 0u, {0, 0, 0}};
+        cl = BatchClass{0, 0, k, 0, {}};
         int kend = k;
         while (kend < n && batch_class(jobs[order[kend]].radius, jobs[order[kend]].dtype) == c)
             ++kend;

@@ -27,8 +27,8 @@ struct BatchClass {
     int njobs;       // jobs in this class
     int job_begin;   // index of its first job in `jobs`
     int variant;     // tile variant of the class
-    unsigned next;   // queue mode: next tile to hand out (uploaded as 0)
-    int pad[3];
+    // queue mode: tiles handed out so far from each XCD's range (uploaded as 0)
+    unsigned next[kXcds];
 };
 
 constexpr int kClasses = 2 * LNF_RADIUS_MAX;  // (radius, voxel type)
@@ -73,9 +73,12 @@ __device__ __forceinline__ const BatchJobDesc& job_of(const BatchTable* tab, con
 
 // Runs body(job, x0, y0, z0, z1, tid) on tiles of class `cls` with TX x TY
 // output tiles.  Grid mode: workgroup b takes class tile b (XCD-aware order).
-// Queue mode: each workgroup takes tiles from the class counter until none is
-// left (the grid is the resident workgroups, not the tiles), with tile_tid as
-// the thread index; s_t is one LDS word.
+// Queue mode (the grid is the resident workgroups, not the tiles): the class's
+// tiles are cut into one contiguous range per XCD, as xcd_tile does; a
+// workgroup takes tiles from the counter of its own XCD's range (workgroups
+// reach the XCDs round-robin by id) until that range is done, then from the
+// other ranges in turn, so neighbouring tiles, which share halo rows, run on
+// one XCD and its L2.  tile_tid is the thread index; s_t is one LDS word.
 template <int TX, int TY, bool QUEUE, typename F>
 __device__ __forceinline__ void for_class_tiles(BatchTable* tab, int cls, int* s_t, F&& body)
 {
@@ -93,13 +96,19 @@ __device__ __forceinline__ void for_class_tiles(BatchTable* tab, int cls, int* s
     if constexpr (!QUEUE) {
         run(xcd_tile(blockIdx.x, total), (int)threadIdx.x);
     } else {
-        for (;;) {
-            if (threadIdx.x == 0) *s_t = (int)atomicAdd(&tab->c[cls].next, 1u);
-            __syncthreads();
-            const int t = *s_t;
-            __syncthreads();  // every thread has read s_t before it is written again
-            if (t >= total) break;
-            run(t, tile_tid());
+        const int home = (int)(blockIdx.x % kXcds);
+        const int q = total / kXcds, rem = total % kXcds;
+        for (int h = 0; h < kXcds; ++h) {
+            const int x = (home + h) % kXcds;
+            const int lo = x * q + min(x, rem), n = q + (x < rem ? 1 : 0);
+            for (;;) {
+                if (threadIdx.x == 0) *s_t = (int)atomicAdd(&tab->c[cls].next[x], 1u);
+                __syncthreads();
+                const int i = *s_t;
+                __syncthreads();  // every thread has read s_t before it is written again
+                if (i >= n) break;
+                run(lo + i, tile_tid());
+            }
         }
     }
 }
