@@ -102,13 +102,19 @@ struct PTShape {
     static constexpr int NRAW = LX * LY;
     static constexpr int NZ = (NRAW + THREADS - 1) / THREADS;  // raw columns per thread
     // x-pass: XS centre columns per row segment; consecutive lanes take
-    // consecutive rows of a segment (rows padded to XR).  Cubes run it over
+    // consecutive rows of a segment, XR rows per segment.  Cubes run it over
     // every raw row, crosses over the raw rows through centres (from row r).
+    // Rows padded to a multiple of 8 keep the 16-byte reads of eight lanes in
+    // distinct bank groups; unpadded rows are used where they need fewer
+    // waves (the x-pass runs on as many waves as its items fill: 28 rows x 9
+    // segments fit 4 waves, 32 x 9 take 5, and the fifth shares a SIMD with
+    // the first; MINVAR9 r = 3, 64 x 16 tiles: 551 -> 527 us per 512^3).
     static constexpr int XIN = CROSS ? GY : LY;
     static constexpr int XROW0 = CROSS ? R : 0;
     static constexpr int XS = 8;
     static constexpr int NXS = (GX + XS - 1) / XS;
-    static constexpr int XR = (XIN + 7) / 8 * 8;
+    static constexpr int XR8 = (XIN + 7) / 8 * 8;
+    static constexpr int XR = (XIN * NXS + 63) / 64 < (XR8 * NXS + 63) / 64 ? XIN : XR8;
     static constexpr int NXI = XR * NXS;                  // x-pass work items
     static constexpr int XW = XS + 2 * R;                 // raw values a segment reads
     static constexpr int XW4 = (XW + 3) / 4 * 4;          // ... rounded to 16-byte reads
