@@ -193,9 +193,13 @@ LNF_API int lnf_filter_batch(lnf_handle h, const lnf_job* jobs, int n, hipStream
 /*
  * lnf_filter_batch with an explicit launch mode; both modes give the same
  * bytes.  LNF_BATCH_PERSISTENT launches, per group, as many workgroups as the
- * GPU holds at once, and each takes tiles from an atomic counter in the job
- * table until the group is done (MEAN9 with 64 x 16 tiles, MINVAR9 with its
- * tuned or default tile).  The counters are uploaded as zero with the table,
+ * GPU holds at once; the group's tiles are cut into one contiguous range per
+ * XCD, and each workgroup takes tiles from its own XCD's atomic counter in
+ * the job table, then from the other XCDs' ranges, until the group is done
+ * (MEAN9 with 64 x 16 tiles, MINVAR9 with its tuned or default tile).  The
+ * grid mode is the faster of the two on the workloads measured; the
+ * persistent mode keeps the number of workgroups fixed.  The counters are
+ * uploaded as zero with the table,
  * so both modes can be captured in a HIP graph (no memset node).  Default
  * cluster geometry only.  Errors: as lnf_filter_batch; LNF_EINVAL also for an
  * unknown mode, or LNF_BATCH_PERSISTENT on a context with LNF_GEOM_* flags.
