@@ -194,8 +194,10 @@ LNF_API int lnf_filter_batch(lnf_handle h, const lnf_job* jobs, int n, hipStream
  * lnf_filter_batch with an explicit launch mode; both modes give the same
  * bytes.  LNF_BATCH_PERSISTENT launches, per group, as many workgroups as the
  * GPU holds at once; the group's tiles are cut into one contiguous range per
- * XCD, and each workgroup takes tiles from its own XCD's atomic counter in
- * the job table, then from the other XCDs' ranges, until the group is done
+ * XCD, the workgroups of an XCD deal all but about one round of its range out
+ * among themselves by stride, take the rest from that range's atomic counter
+ * in the job table, then what is left of the other XCDs' ranges, until the
+ * group is done
  * (MEAN9 with 64 x 16 tiles, MINVAR9 with its tuned or default tile).  The
  * grid mode is the faster of the two on the workloads measured; the
  * persistent mode keeps the number of workgroups fixed.  The counters are
@@ -213,7 +215,7 @@ LNF_API int lnf_filter_batch_mode(lnf_handle h, const lnf_job* jobs, int n, hipS
  * lnf_filter_batch (grid mode) for callers that cannot allocate device memory
  * during the call: code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc.  The call allocates nothing: its job table
- * is a static device array of the library (one per GPU, 12,672 bytes for
+ * is a static device array of the library (one per GPU, 20,608 bytes for
  * LNF_BATCH_NOALLOC_MAX jobs, held until the process ends), filled from a
  * host staging slot that lnf_create preallocated; the caller passes the
  * inputs and outputs as for lnf_filter_batch, and the results are the same

@@ -148,7 +148,7 @@ struct StaticBatchTable {
 };
 static_assert(offsetof(StaticBatchTable, jobs) == offsetof(BatchTable, jobs),
               "the static table is a prefix of BatchTable");
-static_assert(sizeof(StaticBatchTable) == 12672, "size stated in lnf.h");
+static_assert(sizeof(StaticBatchTable) == 20608, "size stated in lnf.h");
 static __device__ __align__(256) unsigned char scratch[sizeof(StaticBatchTable)];
 
 std::mutex g_static_mu;

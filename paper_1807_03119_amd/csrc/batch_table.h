@@ -22,13 +22,17 @@ struct BatchJobDesc {
     int pairs;                             // MEAN9 stages element pairs (mean9_pairs_ok)
 };
 
+// Queue mode keeps each XCD's counter in a 128-byte line of its own: device-scope
+// atomics from several XCDs on one line serialise.
+constexpr int kCounterStride = 32;  // unsigned words
+
 struct BatchClass {
     int total;       // tiles in this class
     int njobs;       // jobs in this class
     int job_begin;   // index of its first job in `jobs`
     int variant;     // tile variant of the class
     // queue mode: tiles handed out so far from each XCD's range (uploaded as 0)
-    unsigned next[kXcds];
+    unsigned next[kXcds * kCounterStride];
 };
 
 constexpr int kClasses = 2 * LNF_RADIUS_MAX;  // (radius, voxel type)
@@ -74,11 +78,13 @@ __device__ __forceinline__ const BatchJobDesc& job_of(const BatchTable* tab, con
 // Runs body(job, x0, y0, z0, z1, tid) on tiles of class `cls` with TX x TY
 // output tiles.  Grid mode: workgroup b takes class tile b (XCD-aware order).
 // Queue mode (the grid is the resident workgroups, not the tiles): the class's
-// tiles are cut into one contiguous range per XCD, as xcd_tile does; a
-// workgroup takes tiles from the counter of its own XCD's range (workgroups
-// reach the XCDs round-robin by id) until that range is done, then from the
-// other ranges in turn, so neighbouring tiles, which share halo rows, run on
-// one XCD and its L2.  tile_tid is the thread index; s_t is one LDS word.
+// tiles are cut into one contiguous range per XCD, as xcd_tile does, so
+// neighbouring tiles, which share halo rows, run on one XCD and its L2
+// (workgroups reach the XCDs round-robin by id).  The workgroups of an XCD deal
+// all but about one round of its range out among themselves by stride; the
+// rest they take one tile at a time from the range's counter, and then take
+// what is left of the other ranges from their counters in turn.  tile_tid is
+// the thread index; s_t is one LDS word.
 template <int TX, int TY, bool QUEUE, typename F>
 __device__ __forceinline__ void for_class_tiles(BatchTable* tab, int cls, int* s_t, F&& body)
 {
@@ -96,15 +102,19 @@ __device__ __forceinline__ void for_class_tiles(BatchTable* tab, int cls, int* s
     if constexpr (!QUEUE) {
         run(xcd_tile(blockIdx.x, total), (int)threadIdx.x);
     } else {
-        const int home = (int)(blockIdx.x % kXcds);
+        const int home = (int)(blockIdx.x % kXcds), w = (int)(blockIdx.x / kXcds);
         const int q = total / kXcds, rem = total % kXcds;
         for (int h = 0; h < kXcds; ++h) {
             const int x = (home + h) % kXcds;
             const int lo = x * q + min(x, rem), n = q + (x < rem ? 1 : 0);
+            const int gx = ((int)gridDim.x - x + kXcds - 1) / kXcds;  // workgroups of XCD x
+            const int ns = gx > 0 ? max(n / gx - 1, 0) * gx : 0;       // tiles dealt by stride
+            if (h == 0)
+                for (int i = w; i < ns; i += gx) run(lo + i, tile_tid());
             for (;;) {
-                if (threadIdx.x == 0) *s_t = (int)atomicAdd(&tab->c[cls].next[x], 1u);
+                if (threadIdx.x == 0) *s_t = (int)atomicAdd(&tab->c[cls].next[x * kCounterStride], 1u);
                 __syncthreads();
-                const int i = *s_t;
+                const int i = ns + *s_t;
                 __syncthreads();  // every thread has read s_t before it is written again
                 if (i >= n) break;
                 run(lo + i, tile_tid());
