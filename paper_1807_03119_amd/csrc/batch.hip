@@ -66,14 +66,14 @@ __attribute__((amdgpu_waves_per_eu((MV9Shape<R, WT>::WAVES)))) void minvar9_mult
     BatchTable* __restrict__ tab, int cls, uint32_t gate)
 {
     using S = MV9Shape<R, WT>;
-    __shared__ __align__(16) MV9Smem<R, T, WT> sm;
+    __shared__ __align__(16) MV9Lds<R, T, WT> sm;
     __shared__ int s_t;
     constexpr int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
     for_class_tiles<S::TX, S::TY, QUEUE>(tab, cls, &s_t, [&](const BatchJobDesc& d, int x0,
                                                             int y0, int z0, int z1, int tid) {
-        plane_tile<R, R, kClusterBox, kRuleMinVar9, T, GATE, WT>(
-            sm, static_cast<const T*>(d.in), static_cast<T*>(d.out), Geom{d.nx, d.ny, d.nz}, x0,
-            y0, z0, z1, gate, (double)n, 1.0 / n, tid);
+        minvar9_tile<R, T, GATE, WT>(sm, static_cast<const T*>(d.in), static_cast<T*>(d.out),
+                                     Geom{d.nx, d.ny, d.nz}, x0, y0, z0, z1, gate, (double)n,
+                                     1.0 / n, tid);
     });
 }
 

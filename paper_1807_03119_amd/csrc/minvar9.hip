@@ -14,16 +14,15 @@ __attribute__((amdgpu_waves_per_eu(MV9Shape<R, WT>::WAVES))) void minvar9_planes
     int total, uint32_t gate, double dn, double invn)
 {
     using S = MV9Shape<R, WT>;
-    __shared__ __align__(16) MV9Smem<R, T, WT> sm;
+    __shared__ __align__(16) MV9Lds<R, T, WT> sm;
     const int tile = xcd_tile(blockIdx.x, total);
     const int bx = tile % tiles_x;
     const int rest = tile / tiles_x;
     const int by = rest % tiles_y;
     const int bz = rest / tiles_y;
     const int z0 = bz * zs;
-    plane_tile<R, R, kClusterBox, kRuleMinVar9, T, GATE, WT>(
-        sm, in, out, g, bx * S::TX, by * S::TY, z0, min(z0 + zs, g.nz), gate, dn, invn,
-        (int)threadIdx.x);
+    minvar9_tile<R, T, GATE, WT>(sm, in, out, g, bx * S::TX, by * S::TY, z0, min(z0 + zs, g.nz),
+                                 gate, dn, invn, (int)threadIdx.x);
 }
 
 template <int R, typename T, bool WT>

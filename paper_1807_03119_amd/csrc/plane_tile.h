@@ -157,12 +157,30 @@ struct PTShape {
     static_assert(THREADS % TX == 0 && OPT * OROWS == TY, "gather mapping");
 };
 
-template <int R, int D, int SHAPE, int RULE, typename T, bool WT = false>
+// Values below 2^nq_bits(R) keep every sum of squares that the z- and x-passes
+// of a (2r+1)^3 cube form, (2r+1)^2 squares, below 2^32.
+constexpr int nq_bits(int r)
+{
+    int b = 16;
+    while (b > 0 && (double)(2 * r + 1) * (2 * r + 1) * ((1 << b) - 1.0) * ((1 << b) - 1.0) >= 4294967296.0)
+        --b;
+    return b;
+}
+
+// NQ (narrow squares, MINVAR9 cubes on uint16 data): the z- and x-passes keep
+// the sums of squares in uint32, which is exact while every value is below
+// 2^nq_bits(r) (14, 13, 13, 12 bits for r = 1..4: 12-bit CT data always); the
+// y-pass adds them up in fp64.  The tile body checks the values it loads and
+// gives up when one is too large; the caller then runs the tile again with
+// fp64 sums.
+template <int R, int D, int SHAPE, int RULE, typename T, bool WT = false, bool NQ = false>
 struct PTSmem {
     using S = PTShape<R, D, SHAPE, RULE, WT>;
     // sums of squares: fp64 for uint16 data, staged in LDS as two 32-bit
-    // halves (so they share the 32-bit layout); uint32 for uint8 data
-    using QT = std::conditional_t<sizeof(T) == 1, uint32_t, double>;
+    // halves (so they share the 32-bit layout); uint32 for uint8 data and NQ
+    using QT = std::conditional_t<sizeof(T) == 1 || NQ, uint32_t, double>;
+    // the y-pass sums of squares and the cluster sums Q
+    using YQ = std::conditional_t<sizeof(T) == 1, uint32_t, double>;
     static constexpr bool VAR = S::VAR, CROSS = S::CROSS;
     static constexpr bool WIDE = sizeof(QT) == 8;
     // MINVAR9 centre entries as one 64-bit key v * 2^16 + rounded mean, when
@@ -188,17 +206,24 @@ struct PTSmem {
 };
 
 // dn = n; inv = 1/n (MINVAR9) or 1/(9n) (MEAN9); tid: threadIdx.x (see
-// tile_tid for loops over several tiles).
-template <int R, int D, int SHAPE, int RULE, typename T, bool GATE, bool WT = false>
-__device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
+// tile_tid for loops over several tiles).  NQ: narrow sums of squares; `flag`
+// is an LDS word of the caller's, and the body returns false, with every
+// thread, when a value of the tile is too large for them (whatever it stored
+// is then to be written again).  Otherwise it returns true.
+template <int R, int D, int SHAPE, int RULE, typename T, bool GATE, bool WT = false,
+          bool NQ = false>
+__device__ __forceinline__ bool plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT, NQ>& sm,
                                            const T* __restrict__ in, T* __restrict__ out, Geom g,
                                            int x0, int y0, int z0, int z1, uint32_t gate,
-                                           double dn, double inv, int tid)
+                                           double dn, double inv, int tid, int* flag = nullptr)
 {
     using S = PTShape<R, D, SHAPE, RULE, WT>;
-    using SM = PTSmem<R, D, SHAPE, RULE, T, WT>;
+    using SM = PTSmem<R, D, SHAPE, RULE, T, WT, NQ>;
     using QT = typename SM::QT;
+    using YQ = typename SM::YQ;
     constexpr bool VAR = S::VAR, CROSS = S::CROSS, WIDE = SM::WIDE, PACK = SM::PACK;
+    static_assert(!NQ || (VAR && !CROSS && sizeof(T) == 2), "narrow squares: MINVAR9 cubes, uint16");
+    constexpr uint32_t kNQLimit = 1u << nq_bits(R);
     static_assert(offsetof(SM, vv) % 16 == 0 && offsetof(SM, zb) % 16 == 0 &&
                       offsetof(SM, zq0) % 16 == 0 && offsetof(SM, zq1) % 16 == 0 &&
                       offsetof(SM, ec) % 16 == 0 && offsetof(SM, xb) % 16 == 0 &&
@@ -245,6 +270,9 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
     const int p0 = z0 - D;
     uint32_t zb[S::NZ];
     QT zq[S::NZ];
+    uint32_t orv = 0;  // NQ: OR of every value loaded
+    if constexpr (NQ)
+        if (tid == 0) *flag = 0;
 #pragma unroll
     for (int i = 0; i < S::NZ; ++i) {
         zb[i] = 0;
@@ -258,6 +286,7 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
         for (int i = 0; i < S::NZ; ++i) {
             zb[i] += e[i];
             if constexpr (VAR) zq[i] += sq(e[i]);
+            if constexpr (NQ) orv |= e[i];
         }
     }
     uint32_t en[S::NZ], eo[S::NZ], ec[S::NZ];
@@ -370,7 +399,7 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
     };
 
     // the centre statistics of one centre: MINVAR9 (v, rounded mean), MEAN9 B
-    auto centre_out = [&](int gy, int gx, uint32_t b, QT qv) {
+    auto centre_out = [&](int gy, int gx, uint32_t b, YQ qv) {
         if constexpr (PACK) {
             // v + 2^52 is exact (v < 2^48), so its mantissa field is v
             const double db = (double)b;
@@ -403,8 +432,10 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
                 if constexpr (VAR) {
                     const uint32_t s = en[i] + eo[i];
                     if constexpr (WIDE) zq[i] = __builtin_fma((double)d, (double)s, zq[i]);
+                    else if constexpr (NQ) zq[i] += (uint32_t)d * s;  // modulo 2^32
                     else zq[i] += (uint32_t)(d * (int)s);
                 }
+                if constexpr (NQ) orv |= en[i];
             }
 #pragma unroll
             for (int i = 0; i < S::NZ; ++i) {
@@ -425,7 +456,14 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
             load(en, p + 1 + R);
             load(eo, p - R);
             if constexpr (CROSS) load(ec, p + 1);
+            // NQ: at each block after the first, the values summed so far are
+            // checked (later planes of the block are checked at the next one,
+            // or after the loop)
+            if constexpr (NQ)
+                if (u == 0 && qb > 0 && orv >= kNQLimit) *flag = 1;
             barrier_lds();
+            if constexpr (NQ)
+                if (u == 0 && qb > 0 && *flag) return false;
 
             // 2. cubes: x-pass of the z-sums.  Crosses: x-lines and y-lines
             //    of slice p through every centre.
@@ -464,13 +502,13 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
                 if (yact) {
                     const int rbase = yseg * YS;
                     uint32_t cb[S::YW];
-                    QT cq[S::YW];
+                    YQ cq[S::YW];
 #pragma unroll
                     for (int t = 0; t < S::YW; ++t) {
                         const uint32_t b = sm.xb[(rbase + t) * S::XPB + ycol];
                         cb[t] = t ? cb[t - 1] + b : b;
                         if constexpr (VAR) {
-                            const QT qv = sm.xq[(rbase + t) * SM::XPQ + ycol];
+                            const YQ qv = (YQ)sm.xq[(rbase + t) * SM::XPQ + ycol];
                             cq[t] = t ? cq[t - 1] + qv : qv;
                         }
                     }
@@ -479,8 +517,8 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
                         const int gy = rbase + m;
                         if (m + (S::NYS - 1) * YS < S::GY || gy < S::GY) {
                             const uint32_t b = cb[m + 2 * R] - (m ? cb[m - 1] : 0u);
-                            QT qv = 0;
-                            if constexpr (VAR) qv = cq[m + 2 * R] - (m ? cq[m - 1] : (QT)0);
+                            YQ qv = 0;
+                            if constexpr (VAR) qv = cq[m + 2 * R] - (m ? cq[m - 1] : (YQ)0);
                             centre_out(gy, ycol, b, qv);
                         }
                     }
@@ -569,6 +607,16 @@ __device__ __forceinline__ void plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT>& sm,
             }
         }
     }
+    if constexpr (NQ) {
+        // the last block's values; the second barrier keeps the next tile's
+        // reset of the flag after every thread has read it
+        if (orv >= kNQLimit) *flag = 1;
+        barrier_lds();
+        const bool ok = *flag == 0;
+        barrier_lds();
+        return ok;
+    }
+    return true;
 }
 
 // The paper's cluster geometry (cubes, diagonal offset r) under MINVAR9, as
@@ -578,5 +626,39 @@ template <int R, bool WT = false>
 using MV9Shape = PTShape<R, R, kClusterBox, kRuleMinVar9, WT>;
 template <int R, typename T, bool WT = false>
 using MV9Smem = PTSmem<R, R, kClusterBox, kRuleMinVar9, T, WT>;
+
+// Narrow sums of squares first: uint16 data up to r = 3 (at r = 4 the two
+// bodies in one kernel spill).
+template <int R, typename T>
+constexpr bool mv9_narrow()
+{
+    return sizeof(T) == 2 && R <= 3;
+}
+
+// LDS of a MINVAR9 tile: the narrow and the fp64 layouts share the space.
+template <int R, typename T, bool WT = false>
+struct MV9Lds {
+    union {
+        MV9Smem<R, T, WT> wide;
+        PTSmem<R, R, kClusterBox, kRuleMinVar9, T, WT, mv9_narrow<R, T>()> narrow;
+    };
+    int flag;
+};
+
+// One MINVAR9 tile: uint16 data first with narrow sums of squares, and again
+// with fp64 sums if a value of the tile is too large for them.
+template <int R, typename T, bool GATE, bool WT>
+__device__ __forceinline__ void minvar9_tile(MV9Lds<R, T, WT>& lds, const T* __restrict__ in,
+                                             T* __restrict__ out, Geom g, int x0, int y0, int z0,
+                                             int z1, uint32_t gate, double dn, double inv, int tid)
+{
+    if constexpr (mv9_narrow<R, T>()) {
+        if (plane_tile<R, R, kClusterBox, kRuleMinVar9, T, GATE, WT, true>(
+                lds.narrow, in, out, g, x0, y0, z0, z1, gate, dn, inv, tid, &lds.flag))
+            return;
+    }
+    plane_tile<R, R, kClusterBox, kRuleMinVar9, T, GATE, WT>(lds.wide, in, out, g, x0, y0, z0, z1,
+                                                             gate, dn, inv, tid);
+}
 
 }  // namespace lnf

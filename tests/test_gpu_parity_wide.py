@@ -52,7 +52,7 @@ def _volume(kind, dims=WIDE, seed=11):
     if kind == "u12_hot":
         v = rng.integers(0, 4096, (nz, ny, nx), dtype=np.uint16)
         # a few bright voxels: only the tiles whose halo holds one fall back
-        for x, y, z in ((5, 3, 2), (100, 20, 12), (199, 39, 23)):
+        for x, y, z in ((5, 3, 2), (nx // 2, ny // 2, nz // 2), (nx - 1, ny - 1, nz - 1)):
             v[z, y, x] = 65000
         return v
     raise ValueError(kind)
@@ -117,7 +117,7 @@ def test_wide_mean_filter(kind):
             _same(got, compare.mean_filter(vol, r), f"mean filter {kind} r={r}")
 
 
-@pytest.mark.parametrize("kind", ["u8", "u12", "u16_extreme"])
+@pytest.mark.parametrize("kind", ["u8", "u12", "u16", "u16_extreme", "u12_hot"])
 def test_wide_minvar9_both_tiles(kind):
     from paper_1807_03119_amd.api import Filter
     vol = _volume(kind, dims=(260, 40, 20), seed=14)
@@ -128,6 +128,42 @@ def test_wide_minvar9_both_tiles(kind):
             for variant in (-1, 0, 1):
                 got = f(dev, r, variant=variant).cpu().numpy()
                 _same(got, want, f"minvar9 {kind} r={r} variant {variant}")
+
+
+# (r, b, v): values below 2^b keep the uint32 sums of squares of the z- and
+# x-passes exact; v is the least value whose (2r+1)^2 squares pass 2^32
+NARROW_LIMITS = [(1, 14, 21846), (2, 13, 13108), (3, 13, 9363)]
+
+
+@pytest.mark.parametrize("r,b,v", NARROW_LIMITS)
+@pytest.mark.parametrize("where", ["mid", "end"])
+def test_minvar9_narrow_squares_limit(r, b, v, where):
+    """uint16 MINVAR9 tiles keep their sums of squares in uint32 through the
+    z- and x-passes while every value they load is below 2^b, and run again
+    with fp64 sums once one reaches it.  Whole planes at 2^b - 1 give the
+    largest narrow sums; 2^b, and v (which would wrap the uint32 sums), make
+    the tiles that load them run again, from blocks in mid-strip ("mid") or
+    from the last planes of the volume ("end").  Both tile variants, z-strips
+    of the default, 7 and 40 slices."""
+    from paper_1807_03119_amd.api import Filter
+    m = (2 * r + 1) ** 2
+    assert m * ((1 << b) - 1) ** 2 < 1 << 32 <= m * ((2 << b) - 1) ** 2  # b: the most bits
+    assert m * (v - 1) ** 2 < 1 << 32 <= m * v ** 2
+    rng = np.random.default_rng(40 + r)
+    base = rng.integers(0, 4096, (48, 40, 200), dtype=np.uint16)
+    with Filter(_lib.LNF_MINVAR9, 0) as f:
+        for value in ((1 << b) - 1, 1 << b, v):
+            vol = base.copy()
+            if where == "mid":
+                vol[30:30 + 2 * r + 1] = value
+            else:
+                vol[-1] = value
+            want = oracle.filter_volume(vol, r, oracle.MINVAR9)
+            dev = _dev(vol)
+            for variant in (0, 1):
+                for zs in (0, 7, 40):
+                    got = f(dev, r, variant=variant, zs=zs).cpu().numpy()
+                    _same(got, want, f"r={r} value {value} {where} variant {variant} zs {zs}")
 
 
 def test_tile_config_matches_its_launch():
