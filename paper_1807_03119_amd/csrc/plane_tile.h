@@ -31,7 +31,8 @@
 //      that order; a register ring per output keeps the z - D group for D
 //      planes and the combination with C(z) for D more.
 // Sums of squares are fp64 for uint16 data (below 2^42) and uint32 for uint8
-// data (below 2^26).
+// data (below 2^26); MINVAR9 cubes on uint16 data keep them in uint32 through
+// the z- and x-passes while the tile's values allow it (NQ below).
 #pragma once
 
 #include <cstddef>
