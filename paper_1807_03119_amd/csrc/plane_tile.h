@@ -196,7 +196,9 @@ struct PTSmem {
     static constexpr int QN = VAR ? 1 : 0, CN = CROSS ? 1 : 0;
     QT xq[QN ? a16(S::XROWS * XPQ, sizeof(QT)) : a16(1, sizeof(QT))];
     QT yq[QN * CN ? a16(S::XROWS * XPQ, sizeof(QT)) : a16(1, sizeof(QT))];  // crosses: y-lines of E^2
-    double vv[QN ? a16(S::GY * S::VP, 8) : 2];   // MINVAR9: v, or the packed keys
+    // MINVAR9: v, or the packed keys (two planes for NQ from r = 2, whose
+    // tile body gathers from one plane while the next is written)
+    double vv[QN ? (NQ && R >= 2 ? 2 : 1) * a16(S::GY * S::VP, 8) : 2];
     uint32_t zb[S::ZN];
     uint32_t zq0[QN ? S::ZN : 4];                // uint8: Zq; uint16: low half of Zq
     uint32_t zq1[QN && WIDE ? S::ZN : 4];        // uint16: high half of Zq
@@ -223,7 +225,8 @@ __device__ __forceinline__ bool plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT, NQ>&
     using QT = typename SM::QT;
     using YQ = typename SM::YQ;
     constexpr bool VAR = S::VAR, CROSS = S::CROSS, WIDE = SM::WIDE, PACK = SM::PACK;
-    static_assert(!NQ || (VAR && !CROSS && sizeof(T) == 2), "narrow squares: MINVAR9 cubes, uint16");
+    static_assert(!NQ || (VAR && !CROSS && sizeof(T) == 2 && PACK),
+                  "narrow squares: MINVAR9 cubes, uint16, packed keys");
     constexpr uint32_t kNQLimit = 1u << nq_bits(R);
     static_assert(offsetof(SM, vv) % 16 == 0 && offsetof(SM, zb) % 16 == 0 &&
                       offsetof(SM, zq0) % 16 == 0 && offsetof(SM, zq1) % 16 == 0 &&
@@ -420,134 +423,56 @@ __device__ __forceinline__ bool plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT, NQ>&
     // unrolled block); the planes past the end read clamped slices and store
     // nothing
     const int npl = (z1 - z0) + 2 * D;
-    for (int qb = 0; qb < npl; qb += U) {
+    // NQ tiles from r = 2 run as a pipeline with two barriers per plane: the
+    // y-pass of the previous plane shares a phase with the z-sums of this one,
+    // and its gather a phase with this plane's x-pass; the keys planes
+    // alternate (512^3, 12-bit: r = 3 288 -> 295 Gvoxel/s, r = 2 313 -> 336;
+    // r = 1 was slower, 440 -> 392).  The other tiles take the four phases in
+    // turn, three barriers a plane, in the loop below the pipelined one (kept
+    // apart: folding the two into shared helpers cost r = 1 13 %).
+    constexpr bool PIPE = NQ && R >= 2;
+    if constexpr (PIPE) {
+        constexpr int KSZ = SM::a16(S::GY * VP, 8);  // keys per plane
+        auto kbuf = [&](int q) { return keys + ((q & 1) ? KSZ : 0); };
+        // the packed key of one centre, written to plane kb
+        auto centre_key = [&](uint64_t* kb, int gy, int gx, uint32_t b, YQ qv) {
+            const double db = (double)b;
+            const double vb = __builtin_fma(dn, (double)qv, __builtin_fma(-db, db, 0x1p52));
+            const uint64_t v = __builtin_bit_cast(uint64_t, vb) & ((1ull << 52) - 1);
+            kb[gy * VP + gx] = (v << 16) | round_div_odd(b, inv);
+        };
+        // cluster sums at every centre of the region, as keys in plane kb
+        auto ypass_cubes = [&](uint64_t* kb) {
+            // y-pass: centre row c covers x-pass rows c .. c+2r
+            if (yact) {
+                const int rbase = yseg * YS;
+                uint32_t cb[S::YW];
+                YQ cq[S::YW];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int q = qb + u;
+                for (int t = 0; t < S::YW; ++t) {
+                    const uint32_t b = sm.xb[(rbase + t) * S::XPB + ycol];
+                    cb[t] = t ? cb[t - 1] + b : b;
+                    if constexpr (VAR) {
+                        const YQ qv = (YQ)sm.xq[(rbase + t) * SM::XPQ + ycol];
+                        cq[t] = t ? cq[t - 1] + qv : qv;
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < YS; ++m) {
+                    const int gy = rbase + m;
+                    if (m + (S::NYS - 1) * YS < S::GY || gy < S::GY) {
+                        const uint32_t b = cb[m + 2 * R] - (m ? cb[m - 1] : 0u);
+                        YQ qv = 0;
+                        if constexpr (VAR) qv = cq[m + 2 * R] - (m ? cq[m - 1] : (YQ)0);
+                        centre_key(kb, gy, ycol, b, qv);
+                    }
+                }
+            }
+        };
+        // gather of plane q (ring slot u): C and the corner group of the plane;
+        // the rings finish output q - D
+        auto gather = [&](uint64_t* kb, int u, int q) {
             const int p = p0 + q;
-            // 1. z-sums of plane p (en = slice p+r, eo = slice p-r-1 or zeros)
-#pragma unroll
-            for (int i = 0; i < S::NZ; ++i) {
-                const int d = (int)en[i] - (int)eo[i];
-                zb[i] += (uint32_t)d;
-                if constexpr (VAR) {
-                    const uint32_t s = en[i] + eo[i];
-                    if constexpr (WIDE) zq[i] = __builtin_fma((double)d, (double)s, zq[i]);
-                    else if constexpr (NQ) zq[i] += (uint32_t)d * s;  // modulo 2^32
-                    else zq[i] += (uint32_t)(d * (int)s);
-                }
-                if constexpr (NQ) orv |= en[i];
-            }
-#pragma unroll
-            for (int i = 0; i < S::NZ; ++i) {
-                if (i < S::NZ - 1 || zlast) {
-                    sm.zb[zi[i]] = zb[i];
-                    if constexpr (VAR) {
-                        if constexpr (WIDE) {
-                            const uint64_t w = __builtin_bit_cast(uint64_t, zq[i]);
-                            sm.zq0[zi[i]] = (uint32_t)w;
-                            sm.zq1[zi[i]] = (uint32_t)(w >> 32);
-                        } else {
-                            sm.zq0[zi[i]] = zq[i];
-                        }
-                    }
-                    if constexpr (CROSS) sm.ec[zi[i]] = ec[i];
-                }
-            }
-            load(en, p + 1 + R);
-            load(eo, p - R);
-            if constexpr (CROSS) load(ec, p + 1);
-            // NQ: at each block after the first, the values summed so far are
-            // checked (later planes of the block are checked at the next one,
-            // or after the loop)
-            if constexpr (NQ)
-                if (u == 0 && qb > 0 && orv >= kNQLimit) *flag = 1;
-            barrier_lds();
-            if constexpr (NQ)
-                if (u == 0 && qb > 0 && *flag) return false;
-
-            // 2. cubes: x-pass of the z-sums.  Crosses: x-lines and y-lines
-            //    of slice p through every centre.
-            if constexpr (!CROSS) {
-                xpass(sm.zb, sm.zq0, sm.zq1);
-            } else {
-                xpass(sm.ec, nullptr, nullptr);
-                if (yact) {
-                    // y-line of centre (ycol, c) covers raw rows c .. c+2r of
-                    // raw column ycol + r
-                    const int rbase = yseg * YS;
-                    uint32_t cb[S::YW];
-                    QT cq[S::YW];
-#pragma unroll
-                    for (int t = 0; t < S::YW; ++t) {
-                        const uint32_t e = sm.ec[(rbase + t) * S::ZP + ycol + R];
-                        cb[t] = t ? cb[t - 1] + e : e;
-                        if constexpr (VAR) cq[t] = t ? cq[t - 1] + sq(e) : sq(e);
-                    }
-#pragma unroll
-                    for (int m = 0; m < YS; ++m) {
-                        const int gy = rbase + m;
-                        if (m + (S::NYS - 1) * YS < S::GY || gy < S::GY) {
-                            sm.yb[gy * S::XPB + ycol] = cb[m + 2 * R] - (m ? cb[m - 1] : 0u);
-                            if constexpr (VAR)
-                                sm.yq[gy * SM::XPQ + ycol] = cq[m + 2 * R] - (m ? cq[m - 1] : (QT)0);
-                        }
-                    }
-                }
-            }
-            barrier_lds();
-
-            // 3. cluster sums at every centre of the region
-            if constexpr (!CROSS) {
-                // y-pass: centre row c covers x-pass rows c .. c+2r
-                if (yact) {
-                    const int rbase = yseg * YS;
-                    uint32_t cb[S::YW];
-                    YQ cq[S::YW];
-#pragma unroll
-                    for (int t = 0; t < S::YW; ++t) {
-                        const uint32_t b = sm.xb[(rbase + t) * S::XPB + ycol];
-                        cb[t] = t ? cb[t - 1] + b : b;
-                        if constexpr (VAR) {
-                            const YQ qv = (YQ)sm.xq[(rbase + t) * SM::XPQ + ycol];
-                            cq[t] = t ? cq[t - 1] + qv : qv;
-                        }
-                    }
-#pragma unroll
-                    for (int m = 0; m < YS; ++m) {
-                        const int gy = rbase + m;
-                        if (m + (S::NYS - 1) * YS < S::GY || gy < S::GY) {
-                            const uint32_t b = cb[m + 2 * R] - (m ? cb[m - 1] : 0u);
-                            YQ qv = 0;
-                            if constexpr (VAR) qv = cq[m + 2 * R] - (m ? cq[m - 1] : (YQ)0);
-                            centre_out(gy, ycol, b, qv);
-                        }
-                    }
-                }
-            } else {
-                // z-line (the z-sum at the centre) + x-line + y-line
-                for (int c = tid; c < S::GX * S::GY; c += kT) {
-                    const int gy = c / GX, gx = c - gy * GX;
-                    const int iz = (gy + R) * S::ZP + gx + R;
-                    const int il = gy * S::XPB + gx;
-                    const uint32_t b = sm.zb[iz] + sm.xb[il] + sm.yb[il];
-                    QT qv = 0;
-                    if constexpr (VAR) {
-                        QT zqv;
-                        if constexpr (WIDE)
-                            zqv = __builtin_bit_cast(double, ((uint64_t)sm.zq1[iz] << 32) | sm.zq0[iz]);
-                        else
-                            zqv = sm.zq0[iz];
-                        const int iq = gy * SM::XPQ + gx;
-                        qv = zqv + sm.xq[iq] + sm.yq[iq];
-                    }
-                    centre_out(gy, gx, b, qv);
-                }
-            }
-            barrier_lds();
-
-            // 4. gather: C and the corner group of plane p; the rings finish
-            //    output p - D
             const int ur = (u + U - D % U) % U;  // slot written D planes ago
             const rsrc_t wr = make_rsrc(out + (size_t)max(p - D, 0) * plane,
                                         (q >= 2 * D && q < npl) ? pbytes : 0u);
@@ -559,12 +484,12 @@ __device__ __forceinline__ bool plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT, NQ>&
                 if constexpr (PACK) {
                     // c.v < b.v  <=>  c.key < (b.key & kHigh): the same
                     // first minima as the unpacked branch below
-                    const uint64_t ck = keys[ic];
-                    uint64_t gk = keys[oy * VP + ox];
+                    const uint64_t ck = kb[ic];
+                    uint64_t gk = kb[oy * VP + ox];
 #pragma unroll
                     for (int k = 1; k < 4; ++k) {
                         const int ik = (oy + ((k & 2) ? 2 * D : 0)) * VP + ox + ((k & 1) ? 2 * D : 0);
-                        const uint64_t kk = keys[ik];
+                        const uint64_t kk = kb[ik];
                         gk = kk < (gk & kHigh) ? kk : gk;
                     }
                     o = (uint32_t)(gk < (mk[ur][j] & kHigh) ? gk : mk[ur][j]) & 0xffffu;
@@ -606,8 +531,283 @@ __device__ __forceinline__ bool plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT, NQ>&
                 if (GATE && o < gate) o = 0;
                 buffer_store<T>(o, wr, soff[j], 0u);
             }
+        };
+        for (int qb = 0; qb < npl; qb += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = qb + u;
+                const int p = p0 + q;
+                if (q > 0) ypass_cubes(kbuf(q - 1));
+                // 1. z-sums of plane p (en = slice p+r, eo = slice p-r-1 or zeros)
+#pragma unroll
+                for (int i = 0; i < S::NZ; ++i) {
+                    const int d = (int)en[i] - (int)eo[i];
+                    zb[i] += (uint32_t)d;
+                    if constexpr (VAR) {
+                        const uint32_t s = en[i] + eo[i];
+                        if constexpr (WIDE) zq[i] = __builtin_fma((double)d, (double)s, zq[i]);
+                        else if constexpr (NQ) zq[i] += (uint32_t)d * s;  // modulo 2^32
+                        else zq[i] += (uint32_t)(d * (int)s);
+                    }
+                    if constexpr (NQ) orv |= en[i];
+                }
+#pragma unroll
+                for (int i = 0; i < S::NZ; ++i) {
+                    if (i < S::NZ - 1 || zlast) {
+                        sm.zb[zi[i]] = zb[i];
+                        if constexpr (VAR) {
+                            if constexpr (WIDE) {
+                                const uint64_t w = __builtin_bit_cast(uint64_t, zq[i]);
+                                sm.zq0[zi[i]] = (uint32_t)w;
+                                sm.zq1[zi[i]] = (uint32_t)(w >> 32);
+                            } else {
+                                sm.zq0[zi[i]] = zq[i];
+                            }
+                        }
+                        if constexpr (CROSS) sm.ec[zi[i]] = ec[i];
+                    }
+                }
+                load(en, p + 1 + R);
+                load(eo, p - R);
+                if constexpr (CROSS) load(ec, p + 1);
+                // NQ: at each block after the first, the values summed so far are
+                // checked (later planes of the block are checked at the next one,
+                // or after the loop)
+                if constexpr (NQ)
+                    if (u == 0 && qb > 0 && orv >= kNQLimit) *flag = 1;
+                barrier_lds();
+                if constexpr (NQ)
+                    if (u == 0 && qb > 0 && *flag) return false;
+
+                // 2. cubes: x-pass of the z-sums.  Crosses: x-lines and y-lines
+                //    of slice p through every centre.
+                if constexpr (!CROSS) {
+                    xpass(sm.zb, sm.zq0, sm.zq1);
+                } else {
+                    xpass(sm.ec, nullptr, nullptr);
+                    if (yact) {
+                        // y-line of centre (ycol, c) covers raw rows c .. c+2r of
+                        // raw column ycol + r
+                        const int rbase = yseg * YS;
+                        uint32_t cb[S::YW];
+                        QT cq[S::YW];
+#pragma unroll
+                        for (int t = 0; t < S::YW; ++t) {
+                            const uint32_t e = sm.ec[(rbase + t) * S::ZP + ycol + R];
+                            cb[t] = t ? cb[t - 1] + e : e;
+                            if constexpr (VAR) cq[t] = t ? cq[t - 1] + sq(e) : sq(e);
+                        }
+#pragma unroll
+                        for (int m = 0; m < YS; ++m) {
+                            const int gy = rbase + m;
+                            if (m + (S::NYS - 1) * YS < S::GY || gy < S::GY) {
+                                sm.yb[gy * S::XPB + ycol] = cb[m + 2 * R] - (m ? cb[m - 1] : 0u);
+                                if constexpr (VAR)
+                                    sm.yq[gy * SM::XPQ + ycol] = cq[m + 2 * R] - (m ? cq[m - 1] : (QT)0);
+                            }
+                        }
+                    }
+                }
+                if (q > 0) gather(kbuf(q - 1), (u + U - 1) % U, q - 1);
+                barrier_lds();
+            }
+        }
+        // the y-pass and the gather of the last plane
+        const int ql = (npl + U - 1) / U * U - 1;
+        ypass_cubes(kbuf(ql));
+        barrier_lds();
+        gather(kbuf(ql), U - 1, ql);
+    } else {
+        for (int qb = 0; qb < npl; qb += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = qb + u;
+                const int p = p0 + q;
+                // 1. z-sums of plane p (en = slice p+r, eo = slice p-r-1 or zeros)
+#pragma unroll
+                for (int i = 0; i < S::NZ; ++i) {
+                    const int d = (int)en[i] - (int)eo[i];
+                    zb[i] += (uint32_t)d;
+                    if constexpr (VAR) {
+                        const uint32_t s = en[i] + eo[i];
+                        if constexpr (WIDE) zq[i] = __builtin_fma((double)d, (double)s, zq[i]);
+                        else if constexpr (NQ) zq[i] += (uint32_t)d * s;  // modulo 2^32
+                        else zq[i] += (uint32_t)(d * (int)s);
+                    }
+                    if constexpr (NQ) orv |= en[i];
+                }
+#pragma unroll
+                for (int i = 0; i < S::NZ; ++i) {
+                    if (i < S::NZ - 1 || zlast) {
+                        sm.zb[zi[i]] = zb[i];
+                        if constexpr (VAR) {
+                            if constexpr (WIDE) {
+                                const uint64_t w = __builtin_bit_cast(uint64_t, zq[i]);
+                                sm.zq0[zi[i]] = (uint32_t)w;
+                                sm.zq1[zi[i]] = (uint32_t)(w >> 32);
+                            } else {
+                                sm.zq0[zi[i]] = zq[i];
+                            }
+                        }
+                        if constexpr (CROSS) sm.ec[zi[i]] = ec[i];
+                    }
+                }
+                load(en, p + 1 + R);
+                load(eo, p - R);
+                if constexpr (CROSS) load(ec, p + 1);
+                // NQ: at each block after the first, the values summed so far are
+                // checked (later planes of the block are checked at the next one,
+                // or after the loop)
+                if constexpr (NQ)
+                    if (u == 0 && qb > 0 && orv >= kNQLimit) *flag = 1;
+                barrier_lds();
+                if constexpr (NQ)
+                    if (u == 0 && qb > 0 && *flag) return false;
+
+                // 2. cubes: x-pass of the z-sums.  Crosses: x-lines and y-lines
+                //    of slice p through every centre.
+                if constexpr (!CROSS) {
+                    xpass(sm.zb, sm.zq0, sm.zq1);
+                } else {
+                    xpass(sm.ec, nullptr, nullptr);
+                    if (yact) {
+                        // y-line of centre (ycol, c) covers raw rows c .. c+2r of
+                        // raw column ycol + r
+                        const int rbase = yseg * YS;
+                        uint32_t cb[S::YW];
+                        QT cq[S::YW];
+#pragma unroll
+                        for (int t = 0; t < S::YW; ++t) {
+                            const uint32_t e = sm.ec[(rbase + t) * S::ZP + ycol + R];
+                            cb[t] = t ? cb[t - 1] + e : e;
+                            if constexpr (VAR) cq[t] = t ? cq[t - 1] + sq(e) : sq(e);
+                        }
+#pragma unroll
+                        for (int m = 0; m < YS; ++m) {
+                            const int gy = rbase + m;
+                            if (m + (S::NYS - 1) * YS < S::GY || gy < S::GY) {
+                                sm.yb[gy * S::XPB + ycol] = cb[m + 2 * R] - (m ? cb[m - 1] : 0u);
+                                if constexpr (VAR)
+                                    sm.yq[gy * SM::XPQ + ycol] = cq[m + 2 * R] - (m ? cq[m - 1] : (QT)0);
+                            }
+                        }
+                    }
+                }
+                barrier_lds();
+
+                // 3. cluster sums at every centre of the region
+                if constexpr (!CROSS) {
+                    // y-pass: centre row c covers x-pass rows c .. c+2r
+                    if (yact) {
+                        const int rbase = yseg * YS;
+                        uint32_t cb[S::YW];
+                        YQ cq[S::YW];
+#pragma unroll
+                        for (int t = 0; t < S::YW; ++t) {
+                            const uint32_t b = sm.xb[(rbase + t) * S::XPB + ycol];
+                            cb[t] = t ? cb[t - 1] + b : b;
+                            if constexpr (VAR) {
+                                const YQ qv = (YQ)sm.xq[(rbase + t) * SM::XPQ + ycol];
+                                cq[t] = t ? cq[t - 1] + qv : qv;
+                            }
+                        }
+#pragma unroll
+                        for (int m = 0; m < YS; ++m) {
+                            const int gy = rbase + m;
+                            if (m + (S::NYS - 1) * YS < S::GY || gy < S::GY) {
+                                const uint32_t b = cb[m + 2 * R] - (m ? cb[m - 1] : 0u);
+                                YQ qv = 0;
+                                if constexpr (VAR) qv = cq[m + 2 * R] - (m ? cq[m - 1] : (YQ)0);
+                                centre_out(gy, ycol, b, qv);
+                            }
+                        }
+                    }
+                } else {
+                    // z-line (the z-sum at the centre) + x-line + y-line
+                    for (int c = tid; c < S::GX * S::GY; c += kT) {
+                        const int gy = c / GX, gx = c - gy * GX;
+                        const int iz = (gy + R) * S::ZP + gx + R;
+                        const int il = gy * S::XPB + gx;
+                        const uint32_t b = sm.zb[iz] + sm.xb[il] + sm.yb[il];
+                        QT qv = 0;
+                        if constexpr (VAR) {
+                            QT zqv;
+                            if constexpr (WIDE)
+                                zqv = __builtin_bit_cast(double, ((uint64_t)sm.zq1[iz] << 32) | sm.zq0[iz]);
+                            else
+                                zqv = sm.zq0[iz];
+                            const int iq = gy * SM::XPQ + gx;
+                            qv = zqv + sm.xq[iq] + sm.yq[iq];
+                        }
+                        centre_out(gy, gx, b, qv);
+                    }
+                }
+                barrier_lds();
+
+                // 4. gather: C and the corner group of plane p; the rings finish
+                //    output p - D
+                const int ur = (u + U - D % U) % U;  // slot written D planes ago
+                const rsrc_t wr = make_rsrc(out + (size_t)max(p - D, 0) * plane,
+                                            (q >= 2 * D && q < npl) ? pbytes : 0u);
+#pragma unroll
+                for (int j = 0; j < OPT; ++j) {
+                    const int oy = oyb + j * S::OROWS;
+                    const int ic = (oy + D) * VP + ox + D;
+                    uint32_t o;
+                    if constexpr (PACK) {
+                        // c.v < b.v  <=>  c.key < (b.key & kHigh): the same
+                        // first minima as the unpacked branch below
+                        const uint64_t ck = keys[ic];
+                        uint64_t gk = keys[oy * VP + ox];
+#pragma unroll
+                        for (int k = 1; k < 4; ++k) {
+                            const int ik = (oy + ((k & 2) ? 2 * D : 0)) * VP + ox + ((k & 1) ? 2 * D : 0);
+                            const uint64_t kk = keys[ik];
+                            gk = kk < (gk & kHigh) ? kk : gk;
+                        }
+                        o = (uint32_t)(gk < (mk[ur][j] & kHigh) ? gk : mk[ur][j]) & 0xffffu;
+                        mk[u][j] = ak[ur][j] < (ck & kHigh) ? ak[ur][j] : ck;
+                        ak[u][j] = gk;
+                    } else if constexpr (VAR) {
+                        const double cv = sm.vv[ic];
+                        const uint32_t co = sm.vo[ic];
+                        double gv = sm.vv[oy * VP + ox];
+                        uint32_t go = sm.vo[oy * VP + ox];
+#pragma unroll
+                        for (int k = 1; k < 4; ++k) {
+                            const int ik = (oy + ((k & 2) ? 2 * D : 0)) * VP + ox + ((k & 1) ? 2 * D : 0);
+                            const double v = sm.vv[ik];
+                            if (v < gv) {
+                                gv = v;
+                                go = sm.vo[ik];
+                            }
+                        }
+                        // output p - D: firstmin(C, G(p - 2D)) kept D planes, then G(p)
+                        o = gv < mv[ur][j] ? go : mo[ur][j];
+                        // output p: firstmin(C(p), G(p - D))
+                        const bool ta = av[ur][j] < cv;
+                        mv[u][j] = ta ? av[ur][j] : cv;
+                        mo[u][j] = ta ? ao[ur][j] : co;
+                        av[u][j] = gv;
+                        ao[u][j] = go;
+                    } else {
+                        const uint32_t c = sm.vo[ic];
+                        const uint32_t k = sm.vo[oy * VP + ox] + sm.vo[oy * VP + ox + 2 * D] +
+                                           sm.vo[(oy + 2 * D) * VP + ox] +
+                                           sm.vo[(oy + 2 * D) * VP + ox + 2 * D];
+                        // output p - D: C + K(p - 2D) kept D planes, plus K(p)
+                        o = round_div_odd(mo[ur][j] + k, inv);
+                        // output p: C(p) + K(p - D)
+                        mo[u][j] = c + ao[ur][j];
+                        ao[u][j] = k;
+                    }
+                    if (GATE && o < gate) o = 0;
+                    buffer_store<T>(o, wr, soff[j], 0u);
+                }
+            }
         }
     }
+
     if constexpr (NQ) {
         // the last block's values; the second barrier keeps the next tile's
         // reset of the flag after every thread has read it
