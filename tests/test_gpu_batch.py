@@ -202,6 +202,25 @@ def test_batch_minvar9_wide_tile_groups():
                                           oracle.filter_volume(vols[0], r, oracle.MINVAR9))
 
 
+@pytest.mark.parametrize("r", [2, 3])
+def test_batch_minvar9_narrow_fallback_many_tiles_per_workgroup(r):
+    """uint16 MINVAR9 tiles keep uint32 sums of squares and run again with
+    fp64 sums when they load a value too large for them.  12-bit data with
+    scattered bright voxels make some tiles of each kind; in the queue mode
+    each workgroup takes several tiles in turn (the volume has about two
+    tiles per resident workgroup).  Both launch modes, against the oracle."""
+    rng = np.random.default_rng(90 + r)
+    vol = rng.integers(0, 4096, (64, 512, 512), dtype=np.uint16)
+    pts = rng.integers(0, [64, 512, 512], size=(40, 3))
+    vol[pts[:, 0], pts[:, 1], pts[:, 2]] = 60000
+    want = oracle.filter_volume(vol, r, oracle.MINVAR9)
+    dev = torch.from_numpy(vol).cuda()
+    with _filter("minvar9") as f:
+        for mode in (_lib.LNF_BATCH_GRID, _lib.LNF_BATCH_PERSISTENT):
+            out = f.batch([(dev, r)], mode=mode)[0]
+            np.testing.assert_array_equal(out.cpu().numpy(), want, err_msg=f"mode {mode}")
+
+
 def test_batch_call_captured_in_a_graph_replays_exactly():
     """A batch call (grid and queue mode) captured in a HIP graph: every replay,
     with eager batch calls and synchronisations between the replays, gives the
