@@ -30,6 +30,9 @@
 //      z combines C(z) with the corner groups of planes z - D and z + D, in
 //      that order; a register ring per output keeps the z - D group for D
 //      planes and the combination with C(z) for D more.
+// Each step reads what the previous one wrote to LDS, so a plane takes three
+// barriers; the narrow MINVAR9 tiles from r = 2 overlap steps 3-4 of plane
+// p - 1 with steps 1-2 of plane p instead (two barriers, two keys planes).
 // Sums of squares are fp64 for uint16 data (below 2^42) and uint32 for uint8
 // data (below 2^26); MINVAR9 cubes on uint16 data keep them in uint32 through
 // the z- and x-passes while the tile's values allow it (NQ below).
