@@ -241,19 +241,25 @@ __device__ __forceinline__ bool plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT, NQ>&
     const size_t plane = (size_t)g.nx * g.ny;
     const uint32_t pbytes = (uint32_t)(plane * sizeof(T));
 
-    // ---- raw columns owned for the z-sums
+    // NQ tiles from r = 2 run as a two-barrier pipeline (below)
+    constexpr bool PIPE = NQ && R >= 2;
+    // ---- raw columns owned for the z-sums.  Pipelined tiles rotate them so
+    // that the partial last round falls on the highest threads, whose waves
+    // have no y-pass work in the same phase.
+    constexpr unsigned ZROT = PIPE ? (unsigned)(S::NRAW - (S::NZ - 1) * kT) : 0u;
+    const int zt = PIPE ? (int)(((unsigned)tid + ZROT) % (unsigned)kT) : tid;
     uint32_t off[S::NZ];
     int zi[S::NZ];  // LDS index of each owned column
 #pragma unroll
     for (int i = 0; i < S::NZ; ++i) {
-        const int e = min(tid + i * kT, S::NRAW - 1);
+        const int e = min(zt + i * kT, S::NRAW - 1);
         const int row = e / LX, col = e - row * LX;
         off[i] = (uint32_t)(clampi(y0 - S::E + row, 0, g.ny - 1) * g.nx +
                             clampi(x0 - S::E + col, 0, g.nx - 1)) * (uint32_t)sizeof(T);
         zi[i] = row * S::ZP + col;
     }
     // lanes past the tile in the last round own no column
-    const bool zlast = tid + (S::NZ - 1) * kT < S::NRAW;
+    const bool zlast = zt + (S::NZ - 1) * kT < S::NRAW;
     auto load = [&](uint32_t(&v)[S::NZ], int zs) {
         const rsrc_t rs = make_rsrc(in + (size_t)clampi(zs, 0, g.nz - 1) * plane, pbytes);
 #pragma unroll
@@ -428,12 +434,11 @@ __device__ __forceinline__ bool plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT, NQ>&
     const int npl = (z1 - z0) + 2 * D;
     // NQ tiles from r = 2 run as a pipeline with two barriers per plane: the
     // y-pass of the previous plane shares a phase with the z-sums of this one,
-    // and its gather a phase with this plane's x-pass; the keys planes
-    // alternate (512^3, 12-bit: r = 3 288 -> 295 Gvoxel/s, r = 2 313 -> 336;
-    // r = 1 was slower, 440 -> 392).  The other tiles take the four phases in
+    // and its gather (issued first) a phase with this plane's x-pass; the keys
+    // planes alternate (512^3, 12-bit: r = 3 467 -> 445 us per launch, 288 ->
+    // 302 Gvoxel/s; r = 2 428 -> 394 us; r = 1 was slower, 440 -> 392).  The other tiles take the four phases in
     // turn, three barriers a plane, in the loop below the pipelined one (kept
     // apart: folding the two into shared helpers cost r = 1 13 %).
-    constexpr bool PIPE = NQ && R >= 2;
     if constexpr (PIPE) {
         constexpr int KSZ = SM::a16(S::GY * VP, 8);  // keys per plane
         auto kbuf = [&](int q) { return keys + ((q & 1) ? KSZ : 0); };
@@ -581,6 +586,7 @@ __device__ __forceinline__ bool plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT, NQ>&
                 barrier_lds();
                 if constexpr (NQ)
                     if (u == 0 && qb > 0 && *flag) return false;
+                if (q > 0) gather(kbuf(q - 1), (u + U - 1) % U, q - 1);
 
                 // 2. cubes: x-pass of the z-sums.  Crosses: x-lines and y-lines
                 //    of slice p through every centre.
@@ -611,7 +617,6 @@ __device__ __forceinline__ bool plane_tile(PTSmem<R, D, SHAPE, RULE, T, WT, NQ>&
                         }
                     }
                 }
-                if (q > 0) gather(kbuf(q - 1), (u + U - 1) % U, q - 1);
                 barrier_lds();
             }
         }
